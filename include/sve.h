@@ -1,0 +1,191 @@
+/*
+ * sve.h -- C ABI of the MI355X Saint-Venant--Exner relaxation solver.
+ *
+ * The library advances the coupled shallow-water / Exner system of the
+ * paper (eq. "bedload system"; 2D form of section "2D dune evolution
+ * cases") with the relaxation scheme of section "Numerical method": per
+ * step, a lambda = 0 projection of the relaxation variables (eqs. "relaxh"
+ * ... "relaxqs"), one homogeneous Riemann problem per interface with
+ * celerities bounded as in eq. "ab", and the cell mean of the Riemann
+ * solutions; 2D by the method of lines on a structured mesh (section
+ * "Parallelization").  Bedload closures: Grass (eq. "bedload Grass") and the
+ * threshold laws of eqs. "MPM" ... "Camenen" fed by the Darcy-Weisbach or
+ * Manning/Strickler friction slope (section "Bedload modelling").
+ *
+ * Conventions
+ *   Grid      nx x ny cells on [0, Lx] x [0, Ly]; dx = Lx/nx, dy = Ly/ny;
+ *             cell centres x_i = (i + 1/2) dx.  1D runs use ny = 1 and
+ *             hv = NULL (then Ly is ignored and only bc[0], bc[1] are used).
+ *   Layout    every field is a row-major array of nx*ny doubles, index
+ *             k = j*nx + i (x fastest): structure of arrays h, hu, hv, z_b.
+ *   Units     SI (metres, seconds); g is taken from sve_params.
+ *   Streams   all device work of a context runs on the hipStream_t given to
+ *             its init call (NULL: the default stream).  Entry points that
+ *             return host data synchronise that stream.
+ *   Ownership the library owns every device buffer of a context (double-
+ *             buffered state, per-cell A_g, control block); host arrays and
+ *             caller device arrays passed in are copied and stay the
+ *             caller's.  A context is not thread-safe; use one per stream.
+ *   Errors    0 on success, a negative SVE_ERR_* code otherwise.  Step
+ *             errors (positivity, ordering, non-finite state) are detected
+ *             on the device and are sticky: the context keeps the last state
+ *             that completed without error (and its time), and further steps
+ *             return the same code until the context is re-initialised.
+ */
+#ifndef SVE_H
+#define SVE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+#define SVE_OK               0
+#define SVE_ERR_ARG         (-1)  /* invalid argument (size, h <= 0, NaN, law) */
+#define SVE_ERR_HIP         (-2)  /* HIP runtime failure (allocation, launch)  */
+#define SVE_ERR_POSITIVITY  (-3)  /* an intermediate 1/h of a Riemann fan <= 0,
+                                     or h <= 0 after an update                 */
+#define SVE_ERR_ORDER       (-4)  /* bed-jump quadratic without admissible root */
+#define SVE_ERR_NONFINITE   (-5)  /* non-finite value in the state              */
+#define SVE_ERR_STATE       (-6)  /* call out of order (e.g. backward before
+                                     forward) or context in an error state     */
+
+/* ---- bedload laws (section "Bedload modelling") ------------------------- */
+#define SVE_LAW_GRASS      0  /* q_b = A_g u |u|^(m_g - 1), eq. "bedload Grass" */
+#define SVE_LAW_MPM        1  /* q* = 8 (tau* - tau*_cr)_+^(3/2), eq. "MPM"     */
+#define SVE_LAW_FLVB       2  /* q* = 5.7 (tau* - tau*_cr)_+^(3/2), eq. "FLVB"  */
+#define SVE_LAW_NIELSEN    3  /* q* = 12 sqrt(tau*) (tau* - tau*_cr)_+          */
+#define SVE_LAW_RIBBERINK  4  /* q* = 11 (tau* - tau*_cr)_+^1.65                */
+#define SVE_LAW_CAMENEN    5  /* q* = 12 tau*^1.5 exp(-4.5 tau*_cr / tau*)      */
+
+/* ---- friction slope inside tau_b = rho g h S_f ------------------------- */
+#define SVE_FRIC_STRICKLER 0  /* S_f = |U|^2 / (K_s^2 h^(4/3)), fric_coef = K_s */
+#define SVE_FRIC_MANNING   1  /* S_f = n^2 |U|^2 / h^(4/3),     fric_coef = n   */
+#define SVE_FRIC_DARCY     2  /* S_f = f |U|^2 / (8 g h),       fric_coef = f   */
+
+/* ---- boundary conditions, order {west, east, south, north} -------------- */
+#define SVE_BC_PERIODIC 0  /* wrap around                                      */
+#define SVE_BC_FREE     1  /* ghost cell = copy of the adjacent cell            */
+#define SVE_BC_INFLOW   2  /* ghost (h, hu, hv) = the sve_bc values, z_b copied */
+
+/* ---- storage ----------------------------------------------------------- */
+#define SVE_FP64 0  /* state stored and computed in double                    */
+#define SVE_FP32 1  /* state stored as float, every operation in double       */
+
+typedef struct sve_params {
+    int    law;              /* SVE_LAW_*                                      */
+    double g;                /* gravity [m/s^2]                                */
+    double A_g;              /* Grass constant (used when no A_g field given)  */
+    double m_g;              /* Grass exponent, 1 <= m_g <= 4                   */
+    int    friction;         /* SVE_FRIC_* (threshold laws, momentum friction) */
+    double fric_coef;        /* K_s, n or f                                    */
+    double d_s;              /* mean grain diameter [m]                        */
+    double s;                /* rho_s / rho                                    */
+    double tau_cr;           /* critical Shields number (0.05 in the paper)    */
+    int    momentum_friction;/* 0: eq. "bedload system" as printed; 1: adds
+                                a semi-implicit -g h S_f momentum source       */
+} sve_params;
+
+typedef struct sve_bc {
+    int    kind;             /* SVE_BC_*                                       */
+    double h, hu, hv;        /* Dirichlet values for SVE_BC_INFLOW             */
+} sve_bc;
+
+typedef struct sve_ctx sve_ctx;
+
+/*
+ * Create a context holding the initial state (host arrays).
+ *   h, hu, zb  : nx*ny values each (required); hv: nx*ny values, or NULL for
+ *                a 1D run (ny must then be 1).  h must be > 0 and finite.
+ *   Ag_field   : nx*ny per-cell Grass constants, or NULL for p->A_g.
+ *   bc         : 4 entries {W, E, S, N} (1D: the first 2 are used).
+ *   storage    : SVE_FP64 or SVE_FP32.
+ *   stream     : hipStream_t used for all work of this context (may be NULL).
+ * The time is set to 0 and the first CFL time step is prepared on the device.
+ * Returns SVE_ERR_ARG for invalid sizes, parameters or non-positive depth.
+ */
+int sve_init_state(sve_ctx **ctx, int nx, int ny, double Lx, double Ly,
+                   const double *h, const double *hu, const double *hv,
+                   const double *zb, const double *Ag_field,
+                   const sve_params *p, const sve_bc bc[4], int storage,
+                   void *stream);
+
+/* Same as sve_init_state with device pointers (read on `stream`). */
+int sve_init_state_dev(sve_ctx **ctx, int nx, int ny, double Lx, double Ly,
+                       const double *h, const double *hu, const double *hv,
+                       const double *zb, const double *Ag_field,
+                       const sve_params *p, const sve_bc bc[4], int storage,
+                       void *stream);
+
+/*
+ * Advance n explicit steps with the CFL time step
+ *   dt = cfl / (S_x/dx + S_y/dy)     (1D: cfl dx / S_x),
+ * S the largest outer relaxation wave speed max(|u_L - a/h_L|, |u_R + a/h_R|)
+ * over the interfaces of each direction of the current state (the paper
+ * states no time-step rule; this is the reading the library implements).
+ * With t_end > 0, dt is clipped so that t stops exactly at t_end and later
+ * steps leave the state unchanged.  The time step never returns to the host
+ * between steps.  *t_out (may be NULL) receives the time reached.
+ */
+int sve_step(sve_ctx *ctx, int n, double cfl, double t_end, double *t_out);
+
+/* Advance n steps with a fixed dt > 0 (no CFL reduction). */
+int sve_step_fixed_dt(sve_ctx *ctx, int n, double dt);
+
+/*
+ * Copy the current state to host arrays (nx*ny doubles each; hv may be NULL;
+ * any pointer may be NULL to skip it).  *t, *dt_last and *nsteps receive the
+ * time, the last time step and the number of completed steps (each may be
+ * NULL).  Synchronises the context's stream.
+ */
+int sve_get_state(sve_ctx *ctx, double *h, double *hu, double *hv, double *zb,
+                  double *t, double *dt_last, long long *nsteps);
+
+/* Same as sve_get_state with caller device pointers (written on the stream). */
+int sve_get_state_dev(sve_ctx *ctx, double *h, double *hu, double *hv,
+                      double *zb, double *t, double *dt_last,
+                      long long *nsteps);
+
+/* Release every device buffer of the context.  NULL is accepted. */
+int sve_destroy(sve_ctx *ctx);
+
+/* Static description of an error code. */
+const char *sve_strerror(int code);
+
+/*
+ * Path selection for tests and measurements (not needed in normal use):
+ *   SVE_PATH_FUSED   (default) one kernel per step: update of step n and
+ *                    the wave speeds of step n+1 in a single pass;
+ *   SVE_PATH_SPLIT   two kernels per step (update, then wave speeds);
+ *   SVE_PATH_RESIDENT (1D only, nx <= 8192) one workgroup keeps the whole
+ *                    grid in LDS and runs all n steps in one launch.
+ */
+#define SVE_PATH_FUSED    0
+#define SVE_PATH_SPLIT    1
+#define SVE_PATH_RESIDENT 2
+int sve_set_path(sve_ctx *ctx, int path);
+
+/*
+ * Rows per tile of the fused 2D kernel (8, 16, 32 or 64; default 32).  Each
+ * wavefront owns 61 columns x `rows` rows and recomputes one row and one
+ * column around them, so larger tiles cost less redundant work but give
+ * fewer wavefronts.
+ */
+int sve_set_tile_rows(sve_ctx *ctx, int rows);
+
+/*
+ * Overwrite one value of the device state (field 0..3 = h, hu, hv, z_b; k a
+ * cell index).  Used to test the device-side error detection.
+ */
+int sve_debug_poke(sve_ctx *ctx, int field, long long k, double value);
+
+/*
+ * Time, in milliseconds, of the last sve_step / sve_step_fixed_dt call
+ * between HIP events recorded on the context's stream around its launches.
+ */
+int sve_last_elapsed_ms(sve_ctx *ctx, double *ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SVE_H */

@@ -1,0 +1,40 @@
+// sve_context.hpp -- host-side context of one solver instance.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/sve.h"
+#include "sve_device.hpp"
+
+struct sve_adjoint_state;
+
+struct sve_ctx {
+    sve::Model M;
+    int storage = SVE_FP64;
+    long long N = 0;        // nx * ny
+    long long pitch = 0;    // elements between fields (multiple of 64)
+    void* buf[2] = {nullptr, nullptr};   // double-buffered state, 4 fields each
+    double* Ag = nullptr;   // per-cell Grass constant, or null
+    sve::Ctrl* ctrl = nullptr;
+    sve::Ctrl* h_ctrl = nullptr;         // pinned host mirror of ctrl
+    double* staging = nullptr;           // 4*N doubles for host transfers
+    hipStream_t stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    int cur = 0;                // buffer holding the current state
+    long long nsteps = 0;
+    double t = 0.0, dt_last = 0.0;
+    int path = SVE_PATH_FUSED;
+    int fused_ty = 32;          // tile rows of the fused kernel
+    int sticky = SVE_OK;
+    bool speeds_valid = false;  // slot nsteps%3 holds the speeds of the state
+    double last_ms = 0.0;
+    sve_adjoint_state* adj = nullptr;
+};
+
+namespace sve {
+Model make_model(int nx, int ny, double Lx, double Ly, int dim, const sve_params* p,
+                 const sve_bc* bc);
+}
+
+// Frees the adjoint buffers of a context (defined with the adjoint).
+void sve_adjoint_release(sve_ctx* ctx);

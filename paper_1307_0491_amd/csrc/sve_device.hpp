@@ -1,0 +1,432 @@
+// sve_device.hpp -- device-side physics of the relaxation scheme (gfx950).
+//
+// Per-cell lambda = 0 projection (relaxation variables at equilibrium,
+// section "Numerical method"), bedload closures (section "Bedload
+// modelling") and the exact Riemann solution of the relaxation system
+// (eqs. "relaxh" ... "relaxqs") at one interface.
+//
+// Riemann solution (derived from the relaxation system's jump conditions;
+// the paper defers the explicit solver to its companion analysis):
+//   five waves u - a/H < u - b/H < u < u + b/H < u + a/H, Lagrangian speeds
+//   -a, -b, 0, b, a.  Outer waves keep Z, Omega, u -/+ a tau and
+//   Pi + a^2 tau; the contact keeps u, Pi, Z, Omega; the sediment waves keep
+//   u -/+ b tau and Pi + a^2 tau, carry the Exner jump [Omega] = sigma [Z]
+//   and, with the non-conservative product g H dZ/dx taken on a straight
+//   path with H frozen at H_bar = (h_L + h_R)/2, the depth jump
+//   [tau] = kappa [Z], kappa = g H_bar / (a^2 - b^2).  Eliminating the
+//   intermediate states leaves a quadratic for the bed jump across the left
+//   sediment wave; its root continuous with kappa -> 0 is taken in the form
+//   -2C / (B + sqrt(B^2 - 8 eps C)).
+// Celerities (eq. "ab" and the remark on stronger bounds):
+//   a_f = max(h sqrt(g h)), a_f^2 = g max(h)^3,
+//   b^2 = max(b_L^2, b_R^2, (H_bar u_est)^2, (1e-14 a_f)^2), with the cell
+//   bound b_K^2 = (h u_n)^2 + g h^2 dq_n/du_n and the star-velocity estimate
+//   u_est = (u_L + u_R)/2 - (Pi_R - Pi_L + g H_bar dZ) / (2 a_f),
+//   a^2 = a_f^2 + b^2 (so a > b and kappa = H_bar / max(h)^3).
+// Interface value: the fan state at x/t = 0, waves with sigma < 0 counted
+// as left-going.  Fluxes in fluctuation form for the momentum equation:
+//   F_h = u(0)/tau(0), F_hu^{L,R} = F_h u(0) + Pi(0) + g H_bar (Z(0) - Z_{L,R}),
+//   F_ht = F_h v(0) (transverse velocity carried by the contact), F_z = Omega(0).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sve {
+
+enum { LAW_GRASS = 0, LAW_MPM, LAW_FLVB, LAW_NIELSEN, LAW_RIBBERINK, LAW_CAMENEN };
+enum { FRIC_STRICKLER = 0, FRIC_MANNING = 1, FRIC_DARCY = 2 };
+enum { BC_PERIODIC = 0, BC_FREE = 1, BC_INFLOW = 2 };
+enum { BCW = 0, BCE = 1, BCS = 2, BCN = 3 };
+enum : unsigned { ERR_POS = 1u, ERR_ORD = 2u, ERR_NONFIN = 4u };
+
+constexpr double B_FLOOR = 1e-14;
+
+// Everything a kernel needs about the model and the grid, passed by value.
+struct Model {
+    int law, friction, momentum_friction;
+    int mg_is3, mg_is1;
+    int nx, ny;           // ny == 1 with dim == 1 for 1D
+    int dim;
+    double g, Ag, mg;
+    double K;             // sqrt((s-1) g d^3)
+    double c_const;       // Shields coefficient constant (see closure)
+    double phi_const;     // momentum-friction constant (see friction_phi)
+    double tau_cr;
+    double dx, dy;
+    int bc_kind[4];
+    double bc_h[4], bc_hu[4], bc_hv[4];
+};
+
+// Control block in device memory.  Wave-speed maxima and times are
+// triple-buffered by step index: step n reads slot n%3, accumulates the
+// maxima of step n+1 into slot (n+1)%3 and clears slot (n+2)%3.
+struct Ctrl {
+    unsigned long long smax[3][2];  // bit patterns of max speeds (x, y), >= 0
+    double t[3];
+    double dt_last;
+    unsigned err;
+    int fail_step;
+    int pad[2];
+};
+
+// Projected cell: the lambda = 0 state and the closure.
+struct Cell {
+    double h, hu, hv, z;     // conserved state (as stored)
+    double tau, u, v, Pi;    // 1/h, velocities, pressure g h^2/2
+    double qx, qy;           // bedload flux vector
+    double bx2, by2;         // (h u)^2 + g h^2 dqx/du, (h v)^2 + g h^2 dqy/dv
+    double aK, inv_aK;       // h sqrt(g h) and its inverse
+};
+
+// One side of an interface seen along its normal.
+struct Side {
+    double h, tau, un, ut, Pi, z, q, b2, aK, inv_aK;
+};
+
+struct Flux {
+    double Fh, FhuL, FhuR, Fht, Fz;
+};
+
+__device__ __forceinline__ Side side_x(const Cell& c) {
+    return Side{c.h, c.tau, c.u, c.v, c.Pi, c.z, c.qx, c.bx2, c.aK, c.inv_aK};
+}
+__device__ __forceinline__ Side side_y(const Cell& c) {
+    return Side{c.h, c.tau, c.v, c.u, c.Pi, c.z, c.qy, c.by2, c.aK, c.inv_aK};
+}
+
+// ---------------------------------------------------------------------------
+// Closures (section "Bedload modelling")
+// ---------------------------------------------------------------------------
+// q*(tau*) and dq*/dtau* of the threshold laws (eqs. "MPM" ... "Camenen").
+__device__ __forceinline__ void threshold_law(int law, double theta, double tc,
+                                              double& F, double& dF) {
+    const double e = theta - tc;
+    F = 0.0;
+    dF = 0.0;
+    if (law == LAW_CAMENEN) {
+        if (theta > 0.0) {
+            const double ex = exp(-4.5 * tc / theta);
+            const double sq = sqrt(theta);
+            F = 12.0 * theta * sq * ex;
+            dF = 12.0 * ex * (1.5 * sq + 4.5 * tc / sq);
+        }
+        return;
+    }
+    if (!(e > 0.0)) return;
+    if (law == LAW_MPM) {
+        const double r = sqrt(e);
+        F = 8.0 * e * r;
+        dF = 12.0 * r;
+    } else if (law == LAW_FLVB) {
+        const double r = sqrt(e);
+        F = 5.7 * e * r;
+        dF = 8.55 * r;
+    } else if (law == LAW_NIELSEN) {
+        const double sq = sqrt(theta);
+        F = 12.0 * sq * e;
+        dF = 12.0 * (e / (2.0 * sq) + sq);
+    } else {  // LAW_RIBBERINK
+        const double p = pow(e, 0.65);
+        F = 11.0 * e * p;
+        dF = 18.15 * p;
+    }
+}
+
+// Bedload flux q = (qx, qy) and beta = (dqx/du|v, dqy/dv|u).
+//   Grass (isotropic 2D form): q = A_g |U|^(m-1) (u, v),
+//     beta_x = A_g |U|^(m-1) (m u^2 + v^2) / |U|^2.
+//   Threshold laws: tau* = c |U|^2 with c from the friction slope
+//     (Strickler 1/((s-1) d K_s^2 h^(1/3)), Manning n^2/((s-1) d h^(1/3)),
+//     Darcy f/(8 g (s-1) d)); q = K q*(tau*) U/|U|, K = sqrt((s-1) g d^3),
+//     beta_x = K [q*'(tau*) 2 c u^2/|U| + q*(tau*) v^2/|U|^3].
+__device__ __forceinline__ void closure(const Model& M, double h, double u,
+                                        double v, double Ag, double& qx,
+                                        double& qy, double& bx, double& by) {
+    const double uu = u * u, vv = v * v;
+    const double w = uu + vv;
+    if (M.law == LAW_GRASS) {
+        if (M.mg_is3) {
+            qx = Ag * w * u;
+            qy = Ag * w * v;
+            bx = Ag * (3.0 * uu + vv);
+            by = Ag * (uu + 3.0 * vv);
+        } else if (M.mg_is1) {
+            qx = Ag * u;
+            qy = Ag * v;
+            bx = Ag;
+            by = Ag;
+        } else {
+            const double p = pow(w, 0.5 * (M.mg - 1.0));
+            qx = Ag * p * u;
+            qy = Ag * p * v;
+            if (w > 0.0) {
+                const double r = 1.0 / w;
+                bx = Ag * p * (M.mg * uu + vv) * r;
+                by = Ag * p * (uu + M.mg * vv) * r;
+            } else {
+                bx = 0.0;
+                by = 0.0;
+            }
+        }
+        return;
+    }
+    const double c = (M.friction == FRIC_DARCY) ? M.c_const : M.c_const / cbrt(h);
+    double F, dF;
+    threshold_law(M.law, c * w, M.tau_cr, F, dF);
+    if (w > 0.0) {
+        const double mag = sqrt(w);
+        const double im = 1.0 / mag;
+        const double Q = M.K * F;
+        qx = Q * u * im;
+        qy = Q * v * im;
+        const double t1 = dF * 2.0 * c * im;
+        const double t2 = F * im / w;
+        bx = M.K * (t1 * uu + t2 * vv);
+        by = M.K * (t1 * vv + t2 * uu);
+    } else {
+        qx = qy = bx = by = 0.0;
+    }
+}
+
+// lambda = 0 projection of one cell.
+__device__ __forceinline__ Cell project(const Model& M, double h, double hu,
+                                        double hv, double z, double Ag) {
+    Cell c;
+    c.h = h;
+    c.hu = hu;
+    c.hv = hv;
+    c.z = z;
+    c.tau = 1.0 / h;
+    c.u = hu * c.tau;
+    c.v = hv * c.tau;
+    c.Pi = 0.5 * M.g * h * h;
+    const double gh = M.g * h;
+    const double sgh = sqrt(gh);
+    c.aK = h * sgh;
+    c.inv_aK = 1.0 / c.aK;
+    double bx, by;
+    closure(M, h, c.u, c.v, Ag, c.qx, c.qy, bx, by);
+    const double gh2 = gh * h;
+    c.bx2 = hu * hu + gh2 * bx;
+    c.by2 = hv * hv + gh2 * by;
+    return c;
+}
+
+// ---------------------------------------------------------------------------
+// Interface celerities
+// ---------------------------------------------------------------------------
+struct Celer {
+    double af2, Hbar, gHbar, dZ, a, b, a2, inv_a, c, kappa;
+};
+
+__device__ __forceinline__ Celer celerities(const Side& L, const Side& R, double g) {
+    Celer C;
+    const double hmax = fmax(L.h, R.h);
+    C.af2 = g * (hmax * hmax * hmax);
+    const double inv_af = fmin(L.inv_aK, R.inv_aK);       // 1 / max(aK)
+    const double a_f = fmax(L.aK, R.aK);
+    C.Hbar = 0.5 * (L.h + R.h);
+    C.gHbar = g * C.Hbar;
+    C.dZ = R.z - L.z;
+    const double u_est = 0.5 * (L.un + R.un) - (R.Pi - L.Pi + C.gHbar * C.dZ) * (0.5 * inv_af);
+    const double hbu = C.Hbar * u_est;
+    const double fl = B_FLOOR * a_f;
+    const double b2 = fmax(fmax(L.b2, R.b2), fmax(hbu * hbu, fl * fl));
+    C.b = sqrt(b2);
+    C.a = sqrt(C.af2 + b2);
+    C.a2 = C.a * C.a;
+    C.inv_a = 1.0 / C.a;
+    C.c = C.af2 / (C.a + C.b);                             // a - b, no cancellation
+    const double tmin = fmin(L.tau, R.tau);
+    C.kappa = C.Hbar * (tmin * tmin * tmin);               // g H_bar / a_f^2
+    return C;
+}
+
+// Largest outer wave speed max(|u_L - a tau_L|, |u_R + a tau_R|).
+__device__ __forceinline__ double iface_speed(const Side& L, const Side& R, double g) {
+    const double hmax = fmax(L.h, R.h);
+    const double af2 = g * (hmax * hmax * hmax);
+    const double inv_af = fmin(L.inv_aK, R.inv_aK);
+    const double a_f = fmax(L.aK, R.aK);
+    const double Hbar = 0.5 * (L.h + R.h);
+    const double dZ = R.z - L.z;
+    const double u_est = 0.5 * (L.un + R.un) - (R.Pi - L.Pi + (g * Hbar) * dZ) * (0.5 * inv_af);
+    const double hbu = Hbar * u_est;
+    const double fl = B_FLOOR * a_f;
+    const double b2 = fmax(fmax(L.b2, R.b2), fmax(hbu * hbu, fl * fl));
+    const double a = sqrt(af2 + b2);
+    return fmax(fabs(L.un - a * L.tau), fabs(R.un + a * R.tau));
+}
+
+// Fluxes of the exact relaxation Riemann solution; returns ERR_* bits.
+__device__ __forceinline__ unsigned iface_flux(const Side& L, const Side& R, double g,
+                                               Flux& F) {
+    const Celer C = celerities(L, R, g);
+    const double a = C.a, b = C.b, c = C.c, a2 = C.a2, kappa = C.kappa, dZ = C.dZ;
+    const double PL = L.Pi + a2 * L.tau;
+    const double PR = R.Pi + a2 * R.tau;
+    const double D = (PR - PL) / a2;
+    const double AL = L.un - a * L.tau;                    // sigma1
+    const double AR = R.un + a * R.tau;                    // sigma5
+    const double kdz = kappa * dZ;
+    const double T0 = (AR - AL - a * D - c * kdz) * (0.5 * C.inv_a);
+    const double bk_a = b * kappa * C.inv_a;
+    const double eps = c * bk_a;
+    const double s2 = AL + c * T0;
+    const double s4 = AR - c * (T0 + D + kdz);
+    const double B = (s4 - s2) + eps * dZ;
+    const double Cq = (R.q - L.q) - 0.5 * (s4 + s2) * dZ;
+    const double disc = B * B - 8.0 * eps * Cq;
+    unsigned err = 0;
+    const double sq = sqrt(fmax(disc, 0.0));
+    const double den = B + sq;
+    if (!(disc >= 0.0) || !(den > 0.0)) err |= ERR_ORD;
+    const double zeta = -2.0 * Cq / den + 0.5 * dZ;
+    const double tau1 = T0 - bk_a * zeta;
+    const double tau2 = tau1 + kappa * zeta;
+    const double tau3 = tau2 + D;
+    const double tau4 = tau1 + D + kdz;
+    if (!(fmin(fmin(tau1, tau2), fmin(tau3, tau4)) > 0.0)) err |= ERR_POS;
+    const double sig2 = AL + c * tau1;
+    const double us = sig2 + b * tau2;                     // sigma3 = u*
+    const double sig4 = AR - c * tau4;
+    // fan state at x/t = 0 (k = number of waves with sigma < 0)
+    double tau0, u0, Pi0, Z0, O0, vt0;
+    if (!(AL < 0.0)) {                                    // k = 0
+        tau0 = L.tau; u0 = L.un; Pi0 = L.Pi; Z0 = L.z; O0 = L.q; vt0 = L.ut;
+    } else if (!(sig2 < 0.0)) {                           // k = 1
+        tau0 = tau1; u0 = AL + a * tau1; Pi0 = PL - a2 * tau1; Z0 = L.z; O0 = L.q; vt0 = L.ut;
+    } else if (!(us < 0.0)) {                             // k = 2
+        tau0 = tau2; u0 = us; Pi0 = PL - a2 * tau2; Z0 = L.z + zeta;
+        O0 = L.q + sig2 * zeta; vt0 = L.ut;
+    } else if (!(sig4 < 0.0)) {                           // k = 3
+        tau0 = tau3; u0 = us; Pi0 = PL - a2 * tau2; Z0 = L.z + zeta;
+        O0 = L.q + sig2 * zeta; vt0 = R.ut;
+    } else if (!(AR < 0.0)) {                             // k = 4
+        tau0 = tau4; u0 = AR - a * tau4; Pi0 = PR - a2 * tau4; Z0 = R.z; O0 = R.q; vt0 = R.ut;
+    } else {                                              // k = 5
+        tau0 = R.tau; u0 = R.un; Pi0 = R.Pi; Z0 = R.z; O0 = R.q; vt0 = R.ut;
+    }
+    F.Fh = u0 / tau0;
+    const double P0 = u0 * F.Fh + Pi0;
+    F.FhuL = P0 + C.gHbar * (Z0 - L.z);
+    F.FhuR = P0 + C.gHbar * (Z0 - R.z);
+    F.Fht = F.Fh * vt0;
+    F.Fz = O0;
+    return err;
+}
+
+// Coefficient phi of the optional semi-implicit momentum friction,
+// -g h S_f = -phi (hu, hv): Darcy f|U|/(8h), Manning/Strickler g n^2 |U| / h^(4/3).
+__device__ __forceinline__ double friction_phi(const Model& M, double h, double speed) {
+    if (M.friction == FRIC_DARCY) return M.phi_const * speed / h;
+    return M.phi_const * speed / (h * cbrt(h));
+}
+
+// ---------------------------------------------------------------------------
+// Grid access with ghost cells
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int wrap(int i, int n) {
+    int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+template <typename T>
+struct StateView {
+    T* h;
+    T* hu;
+    T* hv;   // unused in 1D
+    T* z;
+};
+
+// Load cell (i, j), applying the boundary conditions for indices outside
+// the grid (one ghost layer; corner ghosts are never used by the stencil).
+template <typename T>
+__device__ __forceinline__ void fetch(const Model& M, const StateView<T>& S,
+                                      const double* __restrict__ Agf, int i, int j,
+                                      double& h, double& hu, double& hv, double& z,
+                                      double& Ag) {
+    int ii = i, jj = j, gx = -1, gy = -1;
+    if (i < 0) {
+        if (M.bc_kind[BCW] == BC_PERIODIC) ii = wrap(i, M.nx); else { ii = 0; gx = BCW; }
+    } else if (i >= M.nx) {
+        if (M.bc_kind[BCE] == BC_PERIODIC) ii = wrap(i, M.nx); else { ii = M.nx - 1; gx = BCE; }
+    }
+    if (M.dim == 2) {
+        if (j < 0) {
+            if (M.bc_kind[BCS] == BC_PERIODIC) jj = wrap(j, M.ny); else { jj = 0; gy = BCS; }
+        } else if (j >= M.ny) {
+            if (M.bc_kind[BCN] == BC_PERIODIC) jj = wrap(j, M.ny); else { jj = M.ny - 1; gy = BCN; }
+        }
+    } else {
+        jj = 0;
+    }
+    const long long k = (long long)jj * M.nx + ii;
+    h = (double)S.h[k];
+    hu = (double)S.hu[k];
+    hv = (M.dim == 2) ? (double)S.hv[k] : 0.0;
+    z = (double)S.z[k];
+    Ag = Agf ? Agf[k] : M.Ag;
+    if (gx >= 0 && M.bc_kind[gx] == BC_INFLOW) { h = M.bc_h[gx]; hu = M.bc_hu[gx]; hv = M.bc_hv[gx]; }
+    if (gy >= 0 && M.bc_kind[gy] == BC_INFLOW) { h = M.bc_h[gy]; hu = M.bc_hu[gy]; hv = M.bc_hv[gy]; }
+}
+
+// Ghost cell built from an already known interior state (used for the
+// wave speeds of the new state at non-periodic boundaries).
+__device__ __forceinline__ void ghost_from(const Model& M, int side, double& h,
+                                           double& hu, double& hv) {
+    if (M.bc_kind[side] == BC_INFLOW) { h = M.bc_h[side]; hu = M.bc_hu[side]; hv = M.bc_hv[side]; }
+}
+
+__device__ __forceinline__ double u64_as_double(unsigned long long b) {
+    return __longlong_as_double((long long)b);
+}
+__device__ __forceinline__ unsigned long long double_as_u64(double d) {
+    return (unsigned long long)__double_as_longlong(d);
+}
+
+// Wavefront maximum of non-negative doubles (64 lanes).
+__device__ __forceinline__ double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Step time and time-step of step n from the control block.
+struct StepTime {
+    double dt, t, tnew;
+};
+
+__device__ __forceinline__ StepTime step_time(const Model& M, const Ctrl* ctrl, int n,
+                                              double cfl, double t_end, double fixed_dt) {
+    StepTime st;
+    st.t = ctrl->t[n % 3];
+    if (fixed_dt > 0.0) {
+        st.dt = fixed_dt;
+        st.tnew = st.t + fixed_dt;
+        return st;
+    }
+    const double Sx = u64_as_double(ctrl->smax[n % 3][0]);
+    double dt;
+    if (M.dim == 1) {
+        dt = cfl * M.dx / Sx;
+    } else {
+        const double Sy = u64_as_double(ctrl->smax[n % 3][1]);
+        dt = cfl / (Sx / M.dx + Sy / M.dy);
+    }
+    double tnew = st.t + dt;
+    if (t_end > 0.0) {
+        if (st.t >= t_end) {
+            dt = 0.0;
+            tnew = st.t;
+        } else if (dt >= t_end - st.t) {
+            dt = t_end - st.t;
+            tnew = t_end;
+        }
+    }
+    st.dt = dt;
+    st.tnew = tnew;
+    return st;
+}
+
+}  // namespace sve

@@ -1,0 +1,217 @@
+// sve_resident.hpp -- 1D grids that fit in LDS: one workgroup holds the
+// whole state and runs all requested steps in one launch (the 1D dune of
+// the paper has 1000 cells: a grid-wide pass per step would be launch-bound).
+//
+// Per step: interface fluxes into LDS, barrier, cell update in place,
+// barrier, outer wave speeds of the new state reduced in LDS into the next
+// time step.  The loop ends after n steps, or early when t reaches t_end
+// (the remaining steps would leave the state unchanged) or on an error (the
+// state before the failing step is kept).
+#pragma once
+
+#include "sve_context.hpp"
+#include "sve_kernels.hpp"
+
+namespace sve {
+
+constexpr int RES_BLOCK = 1024;
+constexpr int RES_PER_THREAD = 8;                 // cells per thread (registers)
+constexpr int RES_NMAX = RES_BLOCK * RES_PER_THREAD;
+
+// LDS layout, carved from dynamic shared memory sized for nx.
+struct ResLds {
+    double *h, *hu, *z;                // nx each
+    double *Fh, *FL, *FR, *Fz;         // nx + 1 each
+    double* red;                       // RES_BLOCK / 64
+    unsigned* err;
+};
+
+__host__ __device__ inline size_t res_lds_bytes(int nx) {
+    return sizeof(double) * (3 * (size_t)nx + 4 * ((size_t)nx + 1) + RES_BLOCK / 64) + 16;
+}
+
+__device__ __forceinline__ ResLds res_carve(double* base, int nx) {
+    ResLds L;
+    L.h = base;
+    L.hu = L.h + nx;
+    L.z = L.hu + nx;
+    L.Fh = L.z + nx;
+    L.FL = L.Fh + nx + 1;
+    L.FR = L.FL + nx + 1;
+    L.Fz = L.FR + nx + 1;
+    L.red = L.Fz + nx + 1;
+    L.err = reinterpret_cast<unsigned*>(L.red + RES_BLOCK / 64);
+    return L;
+}
+
+__device__ __forceinline__ void res_cell(const Model& M, const ResLds& L,
+                                         const double* __restrict__ Agf, int i, double& h,
+                                         double& hu, double& z, double& ag) {
+    int ii = i, g = -1;
+    if (i < 0) {
+        if (M.bc_kind[BCW] == BC_PERIODIC) ii = M.nx - 1; else { ii = 0; g = BCW; }
+    } else if (i >= M.nx) {
+        if (M.bc_kind[BCE] == BC_PERIODIC) ii = 0; else { ii = M.nx - 1; g = BCE; }
+    }
+    h = L.h[ii];
+    hu = L.hu[ii];
+    z = L.z[ii];
+    ag = Agf ? Agf[ii] : M.Ag;
+    if (g >= 0 && M.bc_kind[g] == BC_INFLOW) { h = M.bc_h[g]; hu = M.bc_hu[g]; }
+}
+
+__device__ __forceinline__ double res_max_speed(const Model& M, const ResLds& L,
+                                                const double* __restrict__ Agf) {
+    double s = 0.0;
+    for (int m = threadIdx.x; m <= M.nx; m += RES_BLOCK) {
+        double h, hu, z, ag;
+        res_cell(M, L, Agf, m - 1, h, hu, z, ag);
+        const Cell A = project(M, h, hu, 0.0, z, ag);
+        res_cell(M, L, Agf, m, h, hu, z, ag);
+        const Cell B = project(M, h, hu, 0.0, z, ag);
+        s = fmax(s, iface_speed(side_x(A), side_x(B), M.g));
+    }
+    s = wave_max(s);
+    if ((threadIdx.x & 63) == 0) L.red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    double r = 0.0;
+    for (int w = 0; w < RES_BLOCK / 64; ++w) r = fmax(r, L.red[w]);
+    __syncthreads();
+    return r;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(RES_BLOCK)
+k_resident_1d(Model M, StateView<T> S, StateView<T> D, const double* __restrict__ Agf,
+              Ctrl* ctrl, int n0, int nsteps, double cfl, double t_end, double fixed_dt) {
+    extern __shared__ double lds_raw[];
+    ResLds L = res_carve(lds_raw, M.nx);
+    if (ctrl->err) return;
+    const int nx = M.nx;
+    for (int i = threadIdx.x; i < nx; i += RES_BLOCK) {
+        L.h[i] = (double)S.h[i];
+        L.hu[i] = (double)S.hu[i];
+        L.z[i] = (double)S.z[i];
+    }
+    if (threadIdx.x == 0) *L.err = 0u;
+    __syncthreads();
+    const bool cfl_mode = !(fixed_dt > 0.0);
+    double t = ctrl->t[n0 % 3];
+    double S_next = cfl_mode ? u64_as_double(ctrl->smax[n0 % 3][0]) : 0.0;
+    double dt_last = ctrl->dt_last;
+    int done = 0;
+    unsigned err = 0u;
+    for (; done < nsteps; ++done) {
+        if (cfl_mode && t_end > 0.0 && t >= t_end) {   // remaining steps are no-ops
+            done = nsteps;
+            dt_last = 0.0;
+            break;
+        }
+        double dt, tnew;
+        if (cfl_mode) {
+            dt = cfl * M.dx / S_next;
+            tnew = t + dt;
+            if (t_end > 0.0 && dt >= t_end - t) {
+                dt = t_end - t;
+                tnew = t_end;
+            }
+        } else {
+            dt = fixed_dt;
+            tnew = t + dt;
+        }
+        unsigned e = 0u;
+        for (int m = threadIdx.x; m <= nx; m += RES_BLOCK) {
+            double h, hu, z, ag;
+            res_cell(M, L, Agf, m - 1, h, hu, z, ag);
+            const Cell A = project(M, h, hu, 0.0, z, ag);
+            res_cell(M, L, Agf, m, h, hu, z, ag);
+            const Cell B = project(M, h, hu, 0.0, z, ag);
+            Flux F;
+            e |= iface_flux(side_x(A), side_x(B), M.g, F);
+            L.Fh[m] = F.Fh;
+            L.FL[m] = F.FhuL;
+            L.FR[m] = F.FhuR;
+            L.Fz[m] = F.Fz;
+        }
+        __syncthreads();
+        const double lx = dt / M.dx;
+        double nh[RES_PER_THREAD], nhu[RES_PER_THREAD], nz[RES_PER_THREAD];
+        int c = 0;
+        for (int i = threadIdx.x; i < nx; i += RES_BLOCK, ++c) {
+            double hn = L.h[i] - lx * (L.Fh[i + 1] - L.Fh[i]);
+            double hun = L.hu[i] - lx * (L.FL[i + 1] - L.FR[i]);
+            double zn = L.z[i] - lx * (L.Fz[i + 1] - L.Fz[i]);
+            if (M.momentum_friction) {
+                double hvn = 0.0;
+                apply_friction(M, dt, hn, hun, hvn);
+            }
+            e |= check_state(hn, hun, 0.0, zn);
+            nh[c] = hn;
+            nhu[c] = hun;
+            nz[c] = zn;
+        }
+        if (e) atomicOr(L.err, e);
+        __syncthreads();
+        err = *L.err;
+        if (err) break;                              // keep the state before this step
+        c = 0;
+        for (int i = threadIdx.x; i < nx; i += RES_BLOCK, ++c) {
+            L.h[i] = (double)(T)nh[c];
+            L.hu[i] = (double)(T)nhu[c];
+            L.z[i] = (double)(T)nz[c];
+        }
+        __syncthreads();
+        t = tnew;
+        dt_last = dt;
+        if (cfl_mode) S_next = res_max_speed(M, L, Agf);
+    }
+    // write back the last good state into the buffer the host expects
+    const StateView<T>& out = (done & 1) ? D : S;
+    for (int i = threadIdx.x; i < nx; i += RES_BLOCK) {
+        out.h[i] = (T)L.h[i];
+        out.hu[i] = (T)L.hu[i];
+        out.z[i] = (T)L.z[i];
+    }
+    if (threadIdx.x == 0) {
+        const int nend = n0 + done;
+        if (err) {
+            atomicOr(&ctrl->err, err);
+            atomicMin(&ctrl->fail_step, nend);
+        }
+        ctrl->t[nend % 3] = t;
+        ctrl->dt_last = dt_last;
+        ctrl->smax[nend % 3][0] = cfl_mode ? double_as_u64(S_next) : 0ull;
+        ctrl->smax[nend % 3][1] = 0ull;
+        for (int k = 1; k < 3; ++k) {
+            ctrl->smax[(nend + k) % 3][0] = 0ull;
+            ctrl->smax[(nend + k) % 3][1] = 0ull;
+        }
+    }
+}
+
+}  // namespace sve
+
+inline bool resident_supported(const sve_ctx* c) {
+    if (c->M.dim != 1 || c->M.nx > sve::RES_NMAX) return false;
+    int dev = 0, max_lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+        hipSuccess)
+        return false;
+    return sve::res_lds_bytes(c->M.nx) <= (size_t)max_lds;
+}
+
+template <typename T>
+void launch_resident(sve_ctx* c, int n, double cfl, double t_end, double fixed_dt) {
+    using namespace sve;
+    const int src = c->cur, dst = src ^ 1;
+    StateView<T> S, D;
+    T* b0 = static_cast<T*>(c->buf[src]);
+    T* b1 = static_cast<T*>(c->buf[dst]);
+    S = StateView<T>{b0, b0 + c->pitch, b0 + 2 * c->pitch, b0 + 3 * c->pitch};
+    D = StateView<T>{b1, b1 + c->pitch, b1 + 2 * c->pitch, b1 + 3 * c->pitch};
+    hipLaunchKernelGGL(k_resident_1d<T>, dim3(1), dim3(RES_BLOCK), res_lds_bytes(c->M.nx),
+                       c->stream,
+                       c->M, S, D, (const double*)c->Ag, c->ctrl, (int)c->nsteps, n, cfl, t_end,
+                       fixed_dt);
+}

@@ -1,0 +1,115 @@
+"""Error handling of the C ABI on the device: invalid arguments are rejected
+at init, device-detected step errors are sticky and leave the last good
+state (and its time) in place.  Failures are forced from the host (bad
+inputs, a NaN written into the state, an excessive CFL number); every
+kernel still runs to completion."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_helpers import dune2d_case
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sve(gpu_lib):
+    return gpu_lib
+
+
+def per(sve):
+    return [sve.BC(sve.BC_PERIODIC)] * 4
+
+
+def make(sve, case, **kw):
+    return sve.Solver(case["h"], case["hu"], case["zb"], case["hv"], lx=1000.0, ly=1000.0,
+                      bcs=kw.pop("bcs", per(sve)), **kw)
+
+
+def test_rejects_non_positive_or_nan_depth(sve):
+    case = dune2d_case(40, 30)
+    for bad in (0.0, -1.0, np.nan, np.inf):
+        h = case["h"].copy()
+        h[3, 7] = bad
+        with pytest.raises(sve.SveError) as e:
+            sve.Solver(h, case["hu"], case["zb"], case["hv"], lx=1000.0, ly=1000.0, bcs=per(sve))
+        assert e.value.code == -1
+
+
+def test_rejects_invalid_parameters(sve):
+    case = dune2d_case(40, 30)
+    bad = [sve.Params(m_g=5.0), sve.Params(m_g=0.5), sve.Params(law=9), sve.Params(g=-1.0),
+           sve.Params(law=sve.LAW_MPM, d_s=0.0), sve.Params(law=sve.LAW_MPM, fric_coef=0.0)]
+    for p in bad:
+        with pytest.raises(sve.SveError) as e:
+            make(sve, case, params=p)
+        assert e.value.code == -1
+    mixed = [sve.BC(sve.BC_PERIODIC), sve.BC(sve.BC_FREE), sve.BC(), sve.BC()]
+    with pytest.raises(sve.SveError):
+        make(sve, case, bcs=mixed)
+    s = make(sve, case)
+    with pytest.raises(sve.SveError):
+        s.step(1, cfl=0.0)
+    with pytest.raises(sve.SveError):
+        s.step(-1, cfl=0.5)
+    with pytest.raises(sve.SveError):
+        s.step_fixed_dt(1, dt=-1.0)
+    s.close()
+
+
+def test_nan_in_state_is_detected_and_state_kept(sve):
+    case = dune2d_case(70, 50)
+    s = make(sve, case)
+    s.step(10, 0.5)
+    before, t0, _, n0 = s.get_state()
+    s.poke(1, 25 * 70 + 33, float("nan"))
+    with pytest.raises(sve.SveError) as e:
+        s.step(5, 0.5)
+    assert e.value.code == -5                       # non-finite
+    after, t1, _, n1 = s.get_state()
+    assert n1 == n0 and t1 == t0
+    # the kept state is the poked one (last state that started a step)
+    assert np.isnan(after[1][25, 33])
+    mask = np.ones_like(after[0], dtype=bool)
+    mask[25, 33] = False
+    for a, b in zip(after, before):
+        assert np.array_equal(a[mask], b[mask])
+    with pytest.raises(sve.SveError) as e2:        # sticky
+        s.step(1, 0.5)
+    assert e2.value.code == -5
+    s.close()
+
+
+@pytest.mark.parametrize("path", ["fused", "split"])
+def test_excessive_cfl_fails_cleanly(sve, path):
+    case = dune2d_case(64, 64)
+    case["hu"] = case["hu"] * (1.0 + 3.0 * case["zb"])
+    s = make(sve, case, params=sve.Params(A_g=0.5))
+    s.set_path(sve.PATH_FUSED if path == "fused" else sve.PATH_SPLIT)
+    s.step(3, 0.5)
+    good, tg, _, ng = s.get_state()
+    with pytest.raises(sve.SveError) as e:
+        s.step(200, 40.0)
+    assert e.value.code in (-3, -4, -5)
+    kept, tk, _, nk = s.get_state()
+    assert nk >= ng and tk >= tg
+    for a in kept:
+        assert np.all(np.isfinite(a))
+    assert np.all(kept[0] > 0)
+    s.close()
+
+
+def test_1d_resident_error_keeps_state(sve):
+    h, hu, zb, dx = W.dune1d(500)
+    s = sve.Solver(h, hu, zb, lx=1000.0, params=sve.Params(A_g=0.5),
+                   bcs=[sve.BC(sve.BC_PERIODIC)] * 2)
+    s.set_path(sve.PATH_RESIDENT)
+    s.step(10, 0.5)
+    good, tg, _, ng = s.get_state()
+    s.poke(0, 200, -1.0)
+    with pytest.raises(sve.SveError):
+        s.step(50, 0.5)
+    kept, tk, _, nk = s.get_state()
+    assert nk == ng and tk == tg
+    assert kept[0][200] == -1.0
+    s.close()

@@ -1,0 +1,217 @@
+"""GPU path (HIP kernels through the C ABI) against the FP64 oracle, element
+by element on the same seeded inputs.
+
+Tolerances (stated by the build's target): relative L-infinity per field
+<= 1e-12 in FP64; <= 1e-5 for float32 state storage against the oracle's
+float32-storage emulation.  Grids span several tiles of the fused kernel
+(61 columns x 32 rows per wavefront) with ragged tails.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from gpu_helpers import (assert_fields_close, dune2d_case, mpm_case, rel_linf,
+                         to_oracle_bcs, to_oracle_params)
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def sve(gpu_lib):
+    return gpu_lib
+
+
+def grass(sve, Ag=1e-3, mg=3.0, **kw):
+    return sve.Params(law=sve.LAW_GRASS, A_g=Ag, m_g=mg, **kw)
+
+
+def mpm(sve, law=None, friction=None, coef=40.0, **kw):
+    return sve.Params(law=sve.LAW_MPM if law is None else law,
+                      friction=sve.FRIC_STRICKLER if friction is None else friction,
+                      fric_coef=coef, d_s=1e-3, s=2.65, tau_cr=0.05, **kw)
+
+
+def run_pair(sve, case, params, bcs, nsteps, cfl=0.5, path=None, rows=None,
+             storage="fp64", Ag=None, fixed_dt=None, t_end=0.0):
+    s = sve.Solver(case["h"], case["hu"], case["zb"], case.get("hv"), lx=case["lx"],
+                   ly=case.get("ly", 1.0), params=params, bcs=bcs, Ag=Ag, storage=storage)
+    if path is not None:
+        s.set_path(path)
+    if rows is not None:
+        s.set_tile_rows(rows)
+    if case.get("hv") is None:
+        o = O.Oracle1D(case["h"], case["hu"], case["zb"], case["lx"] / case["h"].shape[0],
+                       to_oracle_params(params), to_oracle_bcs(bcs[:2]), Ag=Ag, storage=storage)
+    else:
+        ny, nx = case["h"].shape
+        o = O.Oracle2D(case["h"], case["hu"], case["hv"], case["zb"], case["lx"] / nx,
+                       case["ly"] / ny, to_oracle_params(params), to_oracle_bcs(bcs), Ag=Ag,
+                       storage=storage)
+    if fixed_dt is not None:
+        s.step_fixed_dt(nsteps, fixed_dt)
+        o.step_fixed_dt(nsteps, fixed_dt)
+    else:
+        s.step(nsteps, cfl, t_end)
+        o.step(nsteps, cfl, t_end if t_end > 0 else None)
+    fields, t, dtl, ns = s.get_state()
+    s.close()
+    return fields, t, dtl, ns, o
+
+
+PER = None
+
+
+def per(sve):
+    return [sve.BC(sve.BC_PERIODIC)] * 4
+
+
+@pytest.mark.parametrize("path", ["fused", "split"])
+def test_dune2d_periodic_fp64(sve, path):
+    case = dune2d_case(150, 80)
+    p = sve.PATH_FUSED if path == "fused" else sve.PATH_SPLIT
+    f, t, dtl, ns, o = run_pair(sve, case, grass(sve), per(sve), 60, path=p)
+    assert ns == 60
+    assert t == pytest.approx(o.t, rel=TOL64)
+    assert dtl == pytest.approx(o.dt_last, rel=TOL64)
+    assert_fields_close(f, o.state, TOL64)
+
+
+@pytest.mark.parametrize("rows", [8, 16, 64])
+def test_fused_tile_rows_agree(sve, rows):
+    case = dune2d_case(130, 75)
+    f, t, dtl, ns, o = run_pair(sve, case, grass(sve, Ag=0.05), per(sve), 30, rows=rows)
+    assert t == pytest.approx(o.t, rel=TOL64)
+    assert_fields_close(f, o.state, TOL64)
+
+
+@pytest.mark.parametrize("path", ["fused", "split"])
+def test_mpm_strickler_inflow_free_fp64(sve, path):
+    case = mpm_case(160, 70)
+    bcs = [sve.BC(sve.BC_INFLOW, 0.5, 2.0, 0.0), sve.BC(sve.BC_FREE),
+           sve.BC(sve.BC_FREE), sve.BC(sve.BC_FREE)]
+    p = sve.PATH_FUSED if path == "fused" else sve.PATH_SPLIT
+    f, t, dtl, ns, o = run_pair(sve, case, mpm(sve), bcs, 80, path=p)
+    assert t == pytest.approx(o.t, rel=TOL64)
+    assert_fields_close(f, o.state, TOL64)
+
+
+def test_mpm_fp32_storage(sve):
+    case = mpm_case(160, 70)
+    bcs = [sve.BC(sve.BC_INFLOW, 0.5, 2.0, 0.0), sve.BC(sve.BC_FREE),
+           sve.BC(sve.BC_FREE), sve.BC(sve.BC_FREE)]
+    f, t, dtl, ns, o = run_pair(sve, case, mpm(sve), bcs, 80, storage="fp32")
+    assert t == pytest.approx(o.t, rel=TOL32)
+    assert_fields_close(f, o.state, TOL32)
+    for a in f:
+        assert np.array_equal(a, a.astype(np.float32).astype(np.float64))
+
+
+@pytest.mark.parametrize("mg", [1.0, 1.7, 2.5, 4.0])
+def test_grass_exponent_and_ag_field(sve, mg):
+    case = dune2d_case(100, 66)
+    rng = np.random.default_rng(5)
+    Ag = 1e-2 * (1.0 + 0.3 * rng.uniform(-1, 1, case["h"].shape))
+    case["hv"] = 0.5 * case["zb"]
+    f, t, dtl, ns, o = run_pair(sve, case, grass(sve, Ag=1e-2, mg=mg), per(sve), 40, Ag=Ag)
+    assert t == pytest.approx(o.t, rel=TOL64)
+    assert_fields_close(f, o.state, TOL64)
+
+
+@pytest.mark.parametrize("law", ["FLVB", "NIELSEN", "RIBBERINK", "CAMENEN"])
+@pytest.mark.parametrize("fric", ["MANNING", "DARCY"])
+def test_other_bedload_laws(sve, law, fric):
+    case = mpm_case(90, 40)
+    case["hv"] = 0.2 * np.sin(np.arange(case["h"].size).reshape(case["h"].shape) * 0.01)
+    coef = 0.025 if fric == "MANNING" else 0.05
+    p = mpm(sve, law=getattr(sve, "LAW_" + law), friction=getattr(sve, "FRIC_" + fric),
+            coef=coef)
+    f, t, dtl, ns, o = run_pair(sve, case, p, per(sve), 25)
+    assert_fields_close(f, o.state, TOL64)
+
+
+def test_momentum_friction(sve):
+    case = mpm_case(120, 40)
+    bcs = [sve.BC(sve.BC_INFLOW, 0.5, 2.0, 0.0), sve.BC(sve.BC_FREE),
+           sve.BC(sve.BC_PERIODIC), sve.BC(sve.BC_PERIODIC)]
+    f, t, dtl, ns, o = run_pair(sve, case, mpm(sve, momentum_friction=1), bcs, 40)
+    assert_fields_close(f, o.state, TOL64)
+
+
+def test_fixed_dt_2d(sve):
+    case = dune2d_case(140, 90)
+    f, t, dtl, ns, o = run_pair(sve, case, grass(sve, Ag=0.02), per(sve), 50, fixed_dt=0.01)
+    assert t == pytest.approx(o.t, rel=1e-14)
+    assert_fields_close(f, o.state, TOL64)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 7), (5, 1), (3, 3), (2, 130), (70, 2)])
+def test_tiny_and_degenerate_2d_grids(sve, shape):
+    ny, nx = shape
+    rng = np.random.default_rng(nx * 100 + ny)
+    h = 2.0 + 0.3 * rng.uniform(size=shape)
+    case = dict(h=h, hu=0.5 + 0.2 * rng.uniform(size=shape), hv=0.1 * rng.uniform(size=shape),
+                zb=0.1 * rng.uniform(size=shape), lx=10.0 * nx, ly=10.0 * ny)
+    for bcs in (per(sve), [sve.BC(sve.BC_FREE)] * 4):
+        for path in (sve.PATH_FUSED, sve.PATH_SPLIT):
+            f, t, dtl, ns, o = run_pair(sve, case, grass(sve, Ag=0.01), bcs, 15, path=path)
+            assert_fields_close(f, o.state, TOL64)
+
+
+def test_dune1d_resident_and_split(sve):
+    h, hu, zb, dx = W.dune1d(1000)
+    case = dict(h=h, hu=hu, zb=zb, lx=1000.0)
+    bcs = [sve.BC(sve.BC_PERIODIC)] * 2
+    for path in (sve.PATH_RESIDENT, sve.PATH_SPLIT):
+        f, t, dtl, ns, o = run_pair(sve, case, grass(sve), bcs, 3000, path=path)
+        assert ns == 3000
+        assert t == pytest.approx(o.t, rel=TOL64)
+        assert_fields_close(f, o.state, TOL64, names=("h", "hu", "z"))
+
+
+def test_dune1d_to_t_end(sve):
+    h, hu, zb, dx = W.dune1d(1000)
+    case = dict(h=h, hu=hu, zb=zb, lx=1000.0)
+    bcs = [sve.BC(sve.BC_PERIODIC)] * 2
+    f, t, dtl, ns, o = run_pair(sve, case, grass(sve), bcs, 20000, path=sve.PATH_RESIDENT,
+                                t_end=300.0)
+    assert t == 300.0 and o.t == 300.0
+    assert_fields_close(f, o.state, TOL64, names=("h", "hu", "z"))
+
+
+def test_antidune1d_inflow_free(sve):
+    h, hu, zb, dx = W.antidune1d(1000)
+    case = dict(h=h, hu=hu, zb=zb, lx=24.0)
+    bcs = [sve.BC(sve.BC_INFLOW, 0.5, 1.7, 0.0), sve.BC(sve.BC_FREE)]
+    for path in (sve.PATH_RESIDENT, sve.PATH_SPLIT):
+        f, t, dtl, ns, o = run_pair(sve, case, grass(sve), bcs, 2000, path=path)
+        assert_fields_close(f, o.state, TOL64, names=("h", "hu", "z"))
+
+
+def test_fp32_storage_1d(sve):
+    h, hu, zb, dx = W.dune1d(1000)
+    case = dict(h=h, hu=hu, zb=zb, lx=1000.0)
+    bcs = [sve.BC(sve.BC_PERIODIC)] * 2
+    for path in (sve.PATH_RESIDENT, sve.PATH_SPLIT):
+        f, t, dtl, ns, o = run_pair(sve, case, grass(sve, Ag=0.1), bcs, 500, path=path,
+                                    storage="fp32")
+        assert_fields_close(f, o.state, TOL32, names=("h", "hu", "z"))
+
+
+def test_device_tensor_round_trip(sve):
+    import torch
+    case = dune2d_case(64, 64)
+    dev = [torch.tensor(case[k], device="cuda") for k in ("h", "hu", "zb", "hv")]
+    s = sve.Solver(dev[0], dev[1], dev[2], dev[3], lx=1000.0, ly=1000.0, params=grass(sve),
+                   bcs=per(sve))
+    s.step(10, 0.5)
+    fields, t, dtl, ns = s.get_state_torch()
+    torch.cuda.synchronize()
+    host, t2, _, _ = s.get_state()
+    for a, b in zip(fields, host):
+        assert np.array_equal(a.cpu().numpy(), b)
+    assert t == t2
+    s.close()
