@@ -88,6 +88,10 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         _LOAD_ERROR = f"HIP library not built: {path} (run __graft_entry__.build())"
         raise RuntimeError(_LOAD_ERROR)
+    # torch brings its own HIP runtime (same soname as the system one): load
+    # it first so that the library binds to that single runtime instance and
+    # device pointers and streams from torch are valid in the library.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

@@ -4,6 +4,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -30,7 +31,22 @@ StateView<T> view_of(sve_ctx* c, int b) {
     return v;
 }
 
-int check_hip(hipError_t e) { return e == hipSuccess ? SVE_OK : SVE_ERR_HIP; }
+// HIP failures are reported as SVE_ERR_HIP; with SVE_VERBOSE set in the
+// environment the failing call and the runtime's message go to stderr.
+int hip_fail(hipError_t e, const char* what, int line) {
+    static const bool verbose = std::getenv("SVE_VERBOSE") != nullptr;
+    if (verbose)
+        std::fprintf(stderr, "sve: %s failed at line %d: %s\n", what, line, hipGetErrorString(e));
+    return SVE_ERR_HIP;
+}
+#define HIP_OK(call) ((call) == hipSuccess)
+#define HIP_TRY(call)                                               \
+    do {                                                            \
+        hipError_t e_ = (call);                                     \
+        if (e_ != hipSuccess) return hip_fail(e_, #call, __LINE__); \
+    } while (0)
+
+int check_hip(hipError_t e) { return e == hipSuccess ? SVE_OK : hip_fail(e, "HIP call", 0); }
 
 int code_from_bits(unsigned bits) {
     if (bits & ERR_NONFIN) return SVE_ERR_NONFINITE;
@@ -176,17 +192,14 @@ int run_steps(sve_ctx* c, int n, double cfl, double t_end, double fixed_dt) {
         }
     }
     (void)hipEventRecord(c->ev1, c->stream);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return SVE_ERR_HIP;
+    HIP_TRY(hipGetLastError());
     c->speeds_valid = cfl_mode;
     return SVE_OK;
 }
 
 int finish_steps(sve_ctx* c, int n) {
-    if (hipMemcpyAsync(c->h_ctrl, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream) !=
-        hipSuccess)
-        return SVE_ERR_HIP;
-    if (hipStreamSynchronize(c->stream) != hipSuccess) return SVE_ERR_HIP;
+    HIP_TRY(hipMemcpyAsync(c->h_ctrl, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) c->last_ms = ms;
     const Ctrl& h = *c->h_ctrl;
@@ -230,13 +243,12 @@ int init_common(sve_ctx* c, const double* h, const double* hu, const double* hv,
     hipLaunchKernelGGL(k_reset_ctrl, dim3(1), dim3(64), 0, c->stream, c->ctrl, 0.0);
     hipLaunchKernelGGL(k_load_state<T>, dim3(blocks), dim3(256), 0, c->stream, M, h, hu, hv, z,
                        view_of<T>(c, 0), c->ctrl);
-    if (hipMemcpyAsync(c->h_ctrl, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream) !=
-        hipSuccess)
-        return SVE_ERR_HIP;
-    if (hipStreamSynchronize(c->stream) != hipSuccess) return SVE_ERR_HIP;
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(c->h_ctrl, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
     if (c->h_ctrl->err) return SVE_ERR_ARG;
     launch_speeds<T>(c, 0, 0);
-    if (hipGetLastError() != hipSuccess) return SVE_ERR_HIP;
+    HIP_TRY(hipGetLastError());
     c->speeds_valid = true;
     return SVE_OK;
 }
@@ -264,38 +276,45 @@ int init_impl(sve_ctx** out, int nx, int ny, double Lx, double Ly, const double*
     c->pitch = round_up(c->N, 64);
     const size_t esz = storage == SVE_FP32 ? sizeof(float) : sizeof(double);
     const size_t fields = 4;
-    bool ok = true;
-    for (int b = 0; b < 2; ++b)
-        ok = ok && hipMalloc(&c->buf[b], fields * c->pitch * esz) == hipSuccess;
-    ok = ok && hipMalloc((void**)&c->ctrl, sizeof(Ctrl)) == hipSuccess;
-    ok = ok && hipHostMalloc((void**)&c->h_ctrl, sizeof(Ctrl), hipHostMallocDefault) == hipSuccess;
-    ok = ok && hipEventCreate(&c->ev0) == hipSuccess && hipEventCreate(&c->ev1) == hipSuccess;
-    if (ok && Ag) ok = hipMalloc((void**)&c->Ag, c->N * sizeof(double)) == hipSuccess;
-    if (ok && !dev) ok = hipMalloc((void**)&c->staging, 4 * c->N * sizeof(double)) == hipSuccess;
-    if (!ok) {
+    rc = SVE_OK;
+    auto alloc = [&](hipError_t e, const char* what) {
+        if (rc == SVE_OK && e != hipSuccess) rc = hip_fail(e, what, __LINE__);
+    };
+    for (int b = 0; b < 2; ++b) alloc(hipMalloc(&c->buf[b], fields * c->pitch * esz), "hipMalloc state");
+    alloc(hipMalloc((void**)&c->ctrl, sizeof(Ctrl)), "hipMalloc ctrl");
+    alloc(hipHostMalloc((void**)&c->h_ctrl, sizeof(Ctrl), hipHostMallocDefault), "hipHostMalloc");
+    alloc(hipEventCreate(&c->ev0), "hipEventCreate");
+    alloc(hipEventCreate(&c->ev1), "hipEventCreate");
+    if (Ag) alloc(hipMalloc((void**)&c->Ag, c->N * sizeof(double)), "hipMalloc Ag");
+    if (!dev) alloc(hipMalloc((void**)&c->staging, 4 * c->N * sizeof(double)), "hipMalloc staging");
+    if (rc) {
         sve_destroy(c);
-        return SVE_ERR_HIP;
+        return rc;
     }
     const double *dh = h, *dhu = hu, *dhv = hv, *dz = zb;
     const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     if (!dev) {
         double* s = c->staging;
         const size_t bytes = c->N * sizeof(double);
-        if (hipMemcpyAsync(s, h, bytes, kind, c->stream) != hipSuccess ||
-            hipMemcpyAsync(s + c->N, hu, bytes, kind, c->stream) != hipSuccess ||
-            (hv && hipMemcpyAsync(s + 2 * c->N, hv, bytes, kind, c->stream) != hipSuccess) ||
-            hipMemcpyAsync(s + 3 * c->N, zb, bytes, kind, c->stream) != hipSuccess) {
+        hipError_t e = hipMemcpyAsync(s, h, bytes, kind, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(s + c->N, hu, bytes, kind, c->stream);
+        if (e == hipSuccess && hv) e = hipMemcpyAsync(s + 2 * c->N, hv, bytes, kind, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(s + 3 * c->N, zb, bytes, kind, c->stream);
+        if (e != hipSuccess) {
             sve_destroy(c);
-            return SVE_ERR_HIP;
+            return hip_fail(e, "hipMemcpyAsync initial state", __LINE__);
         }
         dh = s;
         dhu = s + c->N;
         dhv = hv ? s + 2 * c->N : nullptr;
         dz = s + 3 * c->N;
     }
-    if (Ag && hipMemcpyAsync(c->Ag, Ag, c->N * sizeof(double), kind, c->stream) != hipSuccess) {
-        sve_destroy(c);
-        return SVE_ERR_HIP;
+    if (Ag) {
+        const hipError_t e = hipMemcpyAsync(c->Ag, Ag, c->N * sizeof(double), kind, c->stream);
+        if (e != hipSuccess) {
+            sve_destroy(c);
+            return hip_fail(e, "hipMemcpyAsync A_g", __LINE__);
+        }
     }
     rc = storage == SVE_FP32 ? init_common<float>(c, dh, dhu, dhv, dz)
                              : init_common<double>(c, dh, dhu, dhv, dz);
