@@ -139,7 +139,12 @@ void launch_speeds(sve_ctx* c, int buf, int slot) {
     const long long nint = (long long)(M.nx + 1) * M.ny +
                            (M.dim == 2 ? (long long)M.nx * (M.ny + 1) : 0);
     const unsigned blocks = (unsigned)((nint + SPEED_BLOCK - 1) / SPEED_BLOCK);
-    hipLaunchKernelGGL(k_speeds<T>, dim3(blocks), dim3(SPEED_BLOCK), 0, c->stream, M,
+    const int cl = closure_class(M);
+    auto kern = cl == CL_GRASS3 ? k_speeds<T, CL_GRASS3>
+              : cl == CL_GRASS1 ? k_speeds<T, CL_GRASS1>
+              : cl == CL_GRASSM ? k_speeds<T, CL_GRASSM>
+                                : k_speeds<T, CL_THRESH>;
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(SPEED_BLOCK), 0, c->stream, M,
                        view_of<T>(c, buf), (const double*)c->Ag, c->ctrl, slot);
 }
 
@@ -149,7 +154,12 @@ void launch_update(sve_ctx* c, int src, int dst, int n, double cfl, double t_end
     const Model& M = c->M;
     const long long N = (long long)M.nx * M.ny;
     const unsigned blocks = (unsigned)((N + UPDATE_BLOCK - 1) / UPDATE_BLOCK);
-    hipLaunchKernelGGL(k_update<T>, dim3(blocks), dim3(UPDATE_BLOCK), 0, c->stream, M,
+    const int cl = closure_class(M);
+    auto kern = cl == CL_GRASS3 ? k_update<T, CL_GRASS3>
+              : cl == CL_GRASS1 ? k_update<T, CL_GRASS1>
+              : cl == CL_GRASSM ? k_update<T, CL_GRASSM>
+                                : k_update<T, CL_THRESH>;
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(UPDATE_BLOCK), 0, c->stream, M,
                        view_of<T>(c, src), view_of<T>(c, dst), (const double*)c->Ag, c->ctrl,
                        n, cfl, t_end, fixed_dt);
 }
@@ -157,14 +167,8 @@ void launch_update(sve_ctx* c, int src, int dst, int n, double cfl, double t_end
 template <typename T>
 void launch_fused(sve_ctx* c, int src, int dst, int n, double cfl, double t_end,
                   double fixed_dt) {
-    const StateView<T> S = view_of<T>(c, src), D = view_of<T>(c, dst);
-    const double* Ag = c->Ag;
-    switch (c->fused_ty) {
-        case 8: launch_fused_ty<T, 8>(c->M, S, D, Ag, c->ctrl, n, cfl, t_end, fixed_dt, c->stream); break;
-        case 16: launch_fused_ty<T, 16>(c->M, S, D, Ag, c->ctrl, n, cfl, t_end, fixed_dt, c->stream); break;
-        case 64: launch_fused_ty<T, 64>(c->M, S, D, Ag, c->ctrl, n, cfl, t_end, fixed_dt, c->stream); break;
-        default: launch_fused_ty<T, 32>(c->M, S, D, Ag, c->ctrl, n, cfl, t_end, fixed_dt, c->stream); break;
-    }
+    launch_fused_rows<T>(c->M, view_of<T>(c, src), view_of<T>(c, dst), c->Ag, c->ctrl, n, cfl,
+                         t_end, fixed_dt, c->fused_ty, c->stream);
 }
 
 template <typename T>

@@ -42,6 +42,55 @@ enum : unsigned { ERR_POS = 1u, ERR_ORD = 2u, ERR_NONFIN = 4u };
 
 constexpr double B_FLOOR = 1e-14;
 
+// ---------------------------------------------------------------------------
+// Reciprocal, division and square root for positive normal operands.
+// v_rcp_f64 / v_rsq_f64 are accurate to about 2^-24 (measured on gfx950);
+// Newton steps (Newton-Raphson on 1/x and 1/sqrt(x)) and a final residual
+// correction bring the results to about one ulp, with fewer and cheaper
+// instructions than the IEEE-exact sequences.  Non-positive or non-finite
+// operands give non-finite results, which the error checks report.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double frcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+
+// a / x: one Newton step on the reciprocal, then a residual correction.
+__device__ __forceinline__ double fdiv(double a, double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    const double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    const double q = a * r;
+    const double t = __builtin_fma(-x, q, a);
+    return __builtin_fma(t, r, q);
+}
+
+// 1 / sqrt(x): two Newton steps.
+__device__ __forceinline__ double frsq(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    double t = hx * y;
+    double e = __builtin_fma(-t, y, 0.5);
+    y = __builtin_fma(y, e, y);
+    t = hx * y;
+    e = __builtin_fma(-t, y, 0.5);
+    return __builtin_fma(y, e, y);
+}
+
+// sqrt(x): one Newton step on 1/sqrt(x), then a residual correction.
+__device__ __forceinline__ double fsqrt(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double t = (0.5 * x) * y;
+    const double e = __builtin_fma(-t, y, 0.5);
+    y = __builtin_fma(y, e, y);
+    const double s = x * y;
+    const double d = __builtin_fma(-s, s, x);
+    return __builtin_fma(d, 0.5 * y, s);
+}
+
 // Everything a kernel needs about the model and the grid, passed by value.
 struct Model {
     int law, friction, momentum_friction;
@@ -115,11 +164,11 @@ __device__ __forceinline__ void threshold_law(int law, double theta, double tc,
     }
     if (!(e > 0.0)) return;
     if (law == LAW_MPM) {
-        const double r = sqrt(e);
+        const double r = fsqrt(e);
         F = 8.0 * e * r;
         dF = 12.0 * r;
     } else if (law == LAW_FLVB) {
-        const double r = sqrt(e);
+        const double r = fsqrt(e);
         F = 5.7 * e * r;
         dF = 8.55 * r;
     } else if (law == LAW_NIELSEN) {
@@ -133,6 +182,17 @@ __device__ __forceinline__ void threshold_law(int law, double theta, double tc,
     }
 }
 
+// Closure families compiled as separate kernel instantiations, so that the
+// common Grass m_g = 3 path carries no pow/exp/cbrt code (register pressure).
+enum { CL_GRASS3 = 0, CL_GRASS1 = 1, CL_GRASSM = 2, CL_THRESH = 3 };
+
+inline int closure_class(const Model& M) {
+    if (M.law != LAW_GRASS) return CL_THRESH;
+    if (M.mg_is3) return CL_GRASS3;
+    if (M.mg_is1) return CL_GRASS1;
+    return CL_GRASSM;
+}
+
 // Bedload flux q = (qx, qy) and beta = (dqx/du|v, dqy/dv|u).
 //   Grass (isotropic 2D form): q = A_g |U|^(m-1) (u, v),
 //     beta_x = A_g |U|^(m-1) (m u^2 + v^2) / |U|^2.
@@ -140,18 +200,19 @@ __device__ __forceinline__ void threshold_law(int law, double theta, double tc,
 //     (Strickler 1/((s-1) d K_s^2 h^(1/3)), Manning n^2/((s-1) d h^(1/3)),
 //     Darcy f/(8 g (s-1) d)); q = K q*(tau*) U/|U|, K = sqrt((s-1) g d^3),
 //     beta_x = K [q*'(tau*) 2 c u^2/|U| + q*(tau*) v^2/|U|^3].
+template <int CL>
 __device__ __forceinline__ void closure(const Model& M, double h, double u,
                                         double v, double Ag, double& qx,
                                         double& qy, double& bx, double& by) {
     const double uu = u * u, vv = v * v;
     const double w = uu + vv;
-    if (M.law == LAW_GRASS) {
-        if (M.mg_is3) {
+    if (CL != CL_THRESH) {
+        if (CL == CL_GRASS3) {
             qx = Ag * w * u;
             qy = Ag * w * v;
             bx = Ag * (3.0 * uu + vv);
             by = Ag * (uu + 3.0 * vv);
-        } else if (M.mg_is1) {
+        } else if (CL == CL_GRASS1) {
             qx = Ag * u;
             qy = Ag * v;
             bx = Ag;
@@ -175,13 +236,12 @@ __device__ __forceinline__ void closure(const Model& M, double h, double u,
     double F, dF;
     threshold_law(M.law, c * w, M.tau_cr, F, dF);
     if (w > 0.0) {
-        const double mag = sqrt(w);
-        const double im = 1.0 / mag;
+        const double im = frsq(w);                          // 1 / |U|
         const double Q = M.K * F;
         qx = Q * u * im;
         qy = Q * v * im;
         const double t1 = dF * 2.0 * c * im;
-        const double t2 = F * im / w;
+        const double t2 = F * (im * im * im);
         bx = M.K * (t1 * uu + t2 * vv);
         by = M.K * (t1 * vv + t2 * uu);
     } else {
@@ -190,6 +250,7 @@ __device__ __forceinline__ void closure(const Model& M, double h, double u,
 }
 
 // lambda = 0 projection of one cell.
+template <int CL>
 __device__ __forceinline__ Cell project(const Model& M, double h, double hu,
                                         double hv, double z, double Ag) {
     Cell c;
@@ -197,16 +258,18 @@ __device__ __forceinline__ Cell project(const Model& M, double h, double hu,
     c.hu = hu;
     c.hv = hv;
     c.z = z;
-    c.tau = 1.0 / h;
+    // one reciprocal square root gives 1/sqrt(g h), hence 1/h = g r^2,
+    // sqrt(g h) = g h r and 1/(h sqrt(g h)) = r / h
+    const double gh = M.g * h;
+    const double r = frsq(gh);
+    c.tau = M.g * (r * r);
     c.u = hu * c.tau;
     c.v = hv * c.tau;
-    c.Pi = 0.5 * M.g * h * h;
-    const double gh = M.g * h;
-    const double sgh = sqrt(gh);
-    c.aK = h * sgh;
-    c.inv_aK = 1.0 / c.aK;
+    c.Pi = 0.5 * gh * h;
+    c.aK = h * (gh * r);
+    c.inv_aK = c.tau * r;
     double bx, by;
-    closure(M, h, c.u, c.v, Ag, c.qx, c.qy, bx, by);
+    closure<CL>(M, h, c.u, c.v, Ag, c.qx, c.qy, bx, by);
     const double gh2 = gh * h;
     c.bx2 = hu * hu + gh2 * bx;
     c.by2 = hv * hv + gh2 * by;
@@ -233,11 +296,12 @@ __device__ __forceinline__ Celer celerities(const Side& L, const Side& R, double
     const double hbu = C.Hbar * u_est;
     const double fl = B_FLOOR * a_f;
     const double b2 = fmax(fmax(L.b2, R.b2), fmax(hbu * hbu, fl * fl));
-    C.b = sqrt(b2);
-    C.a = sqrt(C.af2 + b2);
+    C.b = fsqrt(b2);
+    const double A2 = C.af2 + b2;
+    C.inv_a = frsq(A2);
+    C.a = A2 * C.inv_a;
     C.a2 = C.a * C.a;
-    C.inv_a = 1.0 / C.a;
-    C.c = C.af2 / (C.a + C.b);                             // a - b, no cancellation
+    C.c = fdiv(C.af2, C.a + C.b);                          // a - b, no cancellation
     const double tmin = fmin(L.tau, R.tau);
     C.kappa = C.Hbar * (tmin * tmin * tmin);               // g H_bar / a_f^2
     return C;
@@ -255,7 +319,7 @@ __device__ __forceinline__ double iface_speed(const Side& L, const Side& R, doub
     const double hbu = Hbar * u_est;
     const double fl = B_FLOOR * a_f;
     const double b2 = fmax(fmax(L.b2, R.b2), fmax(hbu * hbu, fl * fl));
-    const double a = sqrt(af2 + b2);
+    const double a = fsqrt(af2 + b2);
     return fmax(fabs(L.un - a * L.tau), fabs(R.un + a * R.tau));
 }
 
@@ -266,7 +330,7 @@ __device__ __forceinline__ unsigned iface_flux(const Side& L, const Side& R, dou
     const double a = C.a, b = C.b, c = C.c, a2 = C.a2, kappa = C.kappa, dZ = C.dZ;
     const double PL = L.Pi + a2 * L.tau;
     const double PR = R.Pi + a2 * R.tau;
-    const double D = (PR - PL) / a2;
+    const double D = (PR - PL) * (C.inv_a * C.inv_a);
     const double AL = L.un - a * L.tau;                    // sigma1
     const double AR = R.un + a * R.tau;                    // sigma5
     const double kdz = kappa * dZ;
@@ -279,10 +343,10 @@ __device__ __forceinline__ unsigned iface_flux(const Side& L, const Side& R, dou
     const double Cq = (R.q - L.q) - 0.5 * (s4 + s2) * dZ;
     const double disc = B * B - 8.0 * eps * Cq;
     unsigned err = 0;
-    const double sq = sqrt(fmax(disc, 0.0));
+    const double sq = fsqrt(fmax(disc, 1e-300));
     const double den = B + sq;
     if (!(disc >= 0.0) || !(den > 0.0)) err |= ERR_ORD;
-    const double zeta = -2.0 * Cq / den + 0.5 * dZ;
+    const double zeta = fdiv(-2.0 * Cq, den) + 0.5 * dZ;
     const double tau1 = T0 - bk_a * zeta;
     const double tau2 = tau1 + kappa * zeta;
     const double tau3 = tau2 + D;
@@ -291,24 +355,26 @@ __device__ __forceinline__ unsigned iface_flux(const Side& L, const Side& R, dou
     const double sig2 = AL + c * tau1;
     const double us = sig2 + b * tau2;                     // sigma3 = u*
     const double sig4 = AR - c * tau4;
-    // fan state at x/t = 0 (k = number of waves with sigma < 0)
-    double tau0, u0, Pi0, Z0, O0, vt0;
-    if (!(AL < 0.0)) {                                    // k = 0
-        tau0 = L.tau; u0 = L.un; Pi0 = L.Pi; Z0 = L.z; O0 = L.q; vt0 = L.ut;
-    } else if (!(sig2 < 0.0)) {                           // k = 1
-        tau0 = tau1; u0 = AL + a * tau1; Pi0 = PL - a2 * tau1; Z0 = L.z; O0 = L.q; vt0 = L.ut;
-    } else if (!(us < 0.0)) {                             // k = 2
-        tau0 = tau2; u0 = us; Pi0 = PL - a2 * tau2; Z0 = L.z + zeta;
-        O0 = L.q + sig2 * zeta; vt0 = L.ut;
-    } else if (!(sig4 < 0.0)) {                           // k = 3
-        tau0 = tau3; u0 = us; Pi0 = PL - a2 * tau2; Z0 = L.z + zeta;
-        O0 = L.q + sig2 * zeta; vt0 = R.ut;
-    } else if (!(AR < 0.0)) {                             // k = 4
-        tau0 = tau4; u0 = AR - a * tau4; Pi0 = PR - a2 * tau4; Z0 = R.z; O0 = R.q; vt0 = R.ut;
-    } else {                                              // k = 5
-        tau0 = R.tau; u0 = R.un; Pi0 = R.Pi; Z0 = R.z; O0 = R.q; vt0 = R.ut;
-    }
-    F.Fh = u0 / tau0;
+    // fan state at x/t = 0 (k = number of waves with sigma < 0), selected
+    // without branches.  Outer states (k <= 1 or k >= 4) follow from tau by
+    // the outer-wave invariants, u = A -/+ a tau and Pi = P - a^2 tau (k = 0
+    // and k = 5 are the cell states themselves, tau = tau_L or tau_R);
+    // the two states between the sediment waves share u*, Pi*, Z*, Omega*.
+    const bool c1 = AL < 0.0, l2 = sig2 < 0.0, l3 = us < 0.0, l4 = sig4 < 0.0, l5 = AR < 0.0;
+    const bool outer = !l2 || l4;
+    const bool right = l3;                               // state right of the contact
+    const double tauO = right ? (l5 ? R.tau : tau4) : (c1 ? tau1 : L.tau);
+    const double uO = __builtin_fma(right ? -a : a, tauO, right ? AR : AL);
+    const double PiO = __builtin_fma(-a2, tauO, right ? PR : PL);
+    const double tauM = l3 ? tau3 : tau2;
+    const double PiM = __builtin_fma(-a2, tau2, PL);
+    const double tau0 = outer ? tauO : tauM;
+    const double u0 = outer ? uO : us;
+    const double Pi0 = outer ? PiO : PiM;
+    const double Z0 = outer ? (right ? R.z : L.z) : L.z + zeta;
+    const double O0 = outer ? (right ? R.q : L.q) : __builtin_fma(sig2, zeta, L.q);
+    const double vt0 = right ? R.ut : L.ut;
+    F.Fh = fdiv(u0, tau0);
     const double P0 = u0 * F.Fh + Pi0;
     F.FhuL = P0 + C.gHbar * (Z0 - L.z);
     F.FhuR = P0 + C.gHbar * (Z0 - R.z);

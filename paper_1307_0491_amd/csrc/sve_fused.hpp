@@ -1,74 +1,142 @@
 // sve_fused.hpp -- one-pass 2D step: update of step n and the wave speeds
 // of step n+1, one wavefront per tile, marching upward through the rows.
 //
-// Tile: lanes 0..63 hold columns i0-1 .. i0+62 (i0 = 61 * tile index); lanes
-// 1..61 own their column, lane 62 is the ring column and lane 63 its right
-// neighbour.  Rows j0-1 .. j_ring+1 are loaded once each, projected once,
-// and kept in registers for one iteration; x-interfaces use the right
-// neighbour lane's projection (cross-lane shuffle), y-interfaces the
+// Tile: lanes 0..63 hold columns i0-1 .. i0+62 (i0 = 61 * tile index);
+// lanes 1..61 own their column, lane 62 is the ring column and lane 63 its
+// right neighbour.  Rows j0-1 .. j_ring+1 are read once each (the next row
+// is prefetched while the current one is processed), projected once, and
+// kept in registers for one iteration.  x-interfaces take the right lane's
+// projection through a DPP wavefront shift (wave_shl:1), the left
+// interface's flux through wave_shr:1; y-interfaces pair a row with the
 // previous row of the same lane.  The new state is also computed on the ring
 // (one extra column and row, not stored), so the outer wave speeds of the
-// new state can be evaluated on every interface the tile owns (the right
-// and upper interface of each owned cell, plus the boundary interfaces of
+// new state can be evaluated on every interface the tile owns (the right and
+// upper interface of each owned cell, plus the boundary interfaces of
 // non-periodic edges) and reduced into the control block for the next step.
-// Every global access goes through `fetch` (indices wrapped or clamped) or
-// a store guarded by the owned-cell test.
+// Every global access uses wrapped or clamped indices, or is a store guarded
+// by the owned-cell test.
 #pragma once
 
 #include "sve_context.hpp"
 #include "sve_kernels.hpp"
 
+#include <type_traits>
+
 namespace sve {
 
 constexpr int FUSED_OWN = 61;
 constexpr int FUSED_WAVES = 4;
+constexpr int DPP_NEXT = 0x130;   // wave_shl:1 -- lane i reads lane i+1
+constexpr int DPP_PREV = 0x138;   // wave_shr:1 -- lane i reads lane i-1
 
-__device__ __forceinline__ double shdn(double v) { return __shfl_down(v, 1, 64); }
-__device__ __forceinline__ double shup(double v) { return __shfl_up(v, 1, 64); }
+// Lanes without a source lane (lane 63 for DPP_NEXT, lane 0 for DPP_PREV)
+// read 0; their results are never used by an owned cell.
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp_u(unsigned v) {
+    return (unsigned)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xf, 0xf, true);
+}
 
-// Neighbouring lane's view of a projected cell along x (fields used by the
-// interface solver); `down` takes lane+1, otherwise lane-1.
-__device__ __forceinline__ Side shfl_side_x_next(const Cell& c) {
+// The next lane's x view of a projected cell.
+__device__ __forceinline__ Side next_side_x(const Cell& c) {
     Side s;
-    s.h = shdn(c.h);
-    s.tau = shdn(c.tau);
-    s.un = shdn(c.u);
-    s.ut = shdn(c.v);
-    s.Pi = shdn(c.Pi);
-    s.z = shdn(c.z);
-    s.q = shdn(c.qx);
-    s.b2 = shdn(c.bx2);
-    s.aK = shdn(c.aK);
-    s.inv_aK = shdn(c.inv_aK);
+    s.h = dpp<DPP_NEXT>(c.h);
+    s.tau = dpp<DPP_NEXT>(c.tau);
+    s.un = dpp<DPP_NEXT>(c.u);
+    s.ut = dpp<DPP_NEXT>(c.v);
+    s.Pi = dpp<DPP_NEXT>(c.Pi);
+    s.z = dpp<DPP_NEXT>(c.z);
+    s.q = dpp<DPP_NEXT>(c.qx);
+    s.b2 = dpp<DPP_NEXT>(c.bx2);
+    s.aK = dpp<DPP_NEXT>(c.aK);
+    s.inv_aK = dpp<DPP_NEXT>(c.inv_aK);
     return s;
 }
 
-// Lane+1's x view of a projected cell, restricted to what iface_speed reads.
-__device__ __forceinline__ Side shfl_speed_x_next(const Cell& c) {
+// The next lane's x view restricted to what iface_speed reads.
+__device__ __forceinline__ Side next_speed_side(const Side& c) {
     Side s;
-    s.h = shdn(c.h);
-    s.tau = shdn(c.tau);
-    s.un = shdn(c.u);
+    s.h = dpp<DPP_NEXT>(c.h);
+    s.tau = dpp<DPP_NEXT>(c.tau);
+    s.un = dpp<DPP_NEXT>(c.un);
     s.ut = 0.0;
-    s.Pi = shdn(c.Pi);
-    s.z = shdn(c.z);
+    s.Pi = dpp<DPP_NEXT>(c.Pi);
+    s.z = dpp<DPP_NEXT>(c.z);
     s.q = 0.0;
-    s.b2 = shdn(c.bx2);
-    s.aK = shdn(c.aK);
-    s.inv_aK = shdn(c.inv_aK);
+    s.b2 = dpp<DPP_NEXT>(c.b2);
+    s.aK = dpp<DPP_NEXT>(c.aK);
+    s.inv_aK = dpp<DPP_NEXT>(c.inv_aK);
     return s;
 }
 
-template <typename T, int TY>
+struct Raw {
+    double h, hu, hv, z, ag;
+};
+
+// Row r of the tile: wrapped or clamped row index and the INFLOW side that
+// replaces (h, hu, hv) of a ghost row (-1 when none).
+__device__ __forceinline__ void row_index(const Model& M, int r, int& jj, int& gin) {
+    jj = r;
+    int g = -1;
+    if (r < 0) {
+        if (M.bc_kind[BCS] == BC_PERIODIC) jj = wrap(r, M.ny); else { jj = 0; g = BCS; }
+    } else if (r >= M.ny) {
+        if (M.bc_kind[BCN] == BC_PERIODIC) jj = wrap(r, M.ny); else { jj = M.ny - 1; g = BCN; }
+    }
+    gin = (g >= 0 && M.bc_kind[g] == BC_INFLOW) ? g : -1;
+}
+
+template <typename T>
+__device__ __forceinline__ Raw load_row(const Model& M, const StateView<T>& S,
+                                        const double* __restrict__ Agf, int ci, int gxin, int r) {
+    int jj, gyin;
+    row_index(M, r, jj, gyin);
+    const long long k = (long long)jj * M.nx + ci;
+    Raw w;
+    w.h = (double)S.h[k];
+    w.hu = (double)S.hu[k];
+    w.hv = (double)S.hv[k];
+    w.z = (double)S.z[k];
+    w.ag = Agf ? Agf[k] : M.Ag;
+    if (gxin >= 0) { w.h = M.bc_h[gxin]; w.hu = M.bc_hu[gxin]; w.hv = M.bc_hv[gxin]; }
+    if (gyin >= 0) { w.h = M.bc_h[gyin]; w.hu = M.bc_hu[gyin]; w.hv = M.bc_hv[gyin]; }
+    return w;
+}
+
+// Side of a ghost cell next to a cell with side `c` (FREE: the same cell;
+// INFLOW: the Dirichlet (h, hu, hv) with the cell's bed and A_g).
+template <int CL>
+__device__ __forceinline__ Side ghost_side_y(const Model& M, int side, const Side& c, double ag) {
+    if (M.bc_kind[side] != BC_INFLOW) return c;
+    return side_y(project<CL>(M, M.bc_h[side], M.bc_hu[side], M.bc_hv[side], c.z, ag));
+}
+
+// Per-lane state carried from one row to the next.
+struct RowCarry {
+    double h, tau, u, v, Pi, z, qy, by2, aK, inv, hu, hv, ag;   // projected row r-1
+    double dXh, dXm, dXt, dXz;                                 // x-flux differences, row r-1
+    unsigned eX, eY;
+    double Yh, Yt, YR, Yz;                                     // y-flux below row r-1
+    Side N;                                                    // y view, new state of row r-2
+};
+
+template <typename T, int CL, bool SPEEDS>
 __global__ void __launch_bounds__(64 * FUSED_WAVES)
 k_fused(Model M, StateView<T> S, StateView<T> D, const double* __restrict__ Agf, Ctrl* ctrl,
-        int n, double cfl, double t_end, double fixed_dt, int tiles_y) {
+        int n, double cfl, double t_end, double fixed_dt, int TY, int tiles_y) {
     if (ctrl->err) return;
     const StepTime st = step_time(M, ctrl, n, cfl, t_end, fixed_dt);
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) step_bookkeeping(ctrl, n, st);
-    const bool speeds = !(fixed_dt > 0.0);
     const int lane = threadIdx.x & 63;
-    const int ty = blockIdx.y * FUSED_WAVES + (threadIdx.x >> 6);
+    // the wavefront index is uniform: make that visible to the compiler so
+    // that all row bookkeeping stays scalar
+    const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int ty = blockIdx.y * FUSED_WAVES + wid;
     if (ty >= tiles_y) return;                       // whole wavefront
     const int i0 = blockIdx.x * FUSED_OWN;
     const int j0 = ty * TY;
@@ -84,87 +152,126 @@ k_fused(Model M, StateView<T> S, StateView<T> D, const double* __restrict__ Agf,
     const bool yghost_s = (j0 == 0) && M.bc_kind[BCS] != BC_PERIODIC;
     const double lx = st.dt / M.dx, ly = st.dt / M.dy;
 
-    Cell Pp;                      // projected row r-1
-    Flux Xp{0, 0, 0, 0, 0};       // x-flux (lane, lane+1) of row r-1
-    Flux Yp{0, 0, 0, 0, 0};       // y-flux below row r-1
-    unsigned eXp = 0, eYp = 0;
-    Side Np{};                    // y view of the projected new state of row r-2
-    double nh = 0, nhu = 0, nhv = 0, nz = 0;   // new state of row r-2 (north ghost)
-    double agp = 0.0;             // A_g of row r-1
+    // column of this lane: wrapped or clamped, and its INFLOW ghost side
+    int ci = col, gx = -1;
+    if (col < 0) {
+        if (M.bc_kind[BCW] == BC_PERIODIC) ci = wrap(col, M.nx); else { ci = 0; gx = BCW; }
+    } else if (col >= M.nx) {
+        if (M.bc_kind[BCE] == BC_PERIODIC) ci = wrap(col, M.nx); else { ci = M.nx - 1; gx = BCE; }
+    }
+    const int gxin = (gx >= 0 && M.bc_kind[gx] == BC_INFLOW) ? gx : -1;
     double sx = 0.0, sy = 0.0;
 
-    for (int r = j0 - 1; r <= j_ring + 1; ++r) {
-        double h, hu, hv, z, ag;
-        fetch(M, S, Agf, col, r, h, hu, hv, z, ag);
-        const Cell P = project(M, h, hu, hv, z, ag);
-        Flux X{0, 0, 0, 0, 0};
-        unsigned eX = 0;
-        if (r >= j0 && r <= j_ring) eX = iface_flux(side_x(P), shfl_side_x_next(P), M.g, X);
-        Flux Y{0, 0, 0, 0, 0};
-        unsigned eY = 0;
-        if (r >= j0) eY = iface_flux(side_y(Pp), side_y(P), M.g, Y);
-        const int ru = r - 1;                        // row updated in this iteration
-        if (ru >= j0) {
-            const double fl_h = shup(Xp.Fh), fl_m = shup(Xp.FhuR);
-            const double fl_t = shup(Xp.Fht), fl_z = shup(Xp.Fz);
-            const unsigned eXl = (unsigned)__shfl_up((int)eXp, 1, 64);
-            double hn = Pp.h - lx * (Xp.Fh - fl_h) - ly * (Y.Fh - Yp.Fh);
-            double hun = Pp.hu - lx * (Xp.FhuL - fl_m) - ly * (Y.Fht - Yp.Fht);
-            double hvn = Pp.hv - lx * (Xp.Fht - fl_t) - ly * (Y.FhuL - Yp.FhuR);
-            double zn = Pp.z - lx * (Xp.Fz - fl_z) - ly * (Y.Fz - Yp.Fz);
+    // Row r with the row loaded for it in `cur`.  DO_X: x-interfaces of row
+    // r; DO_UPD: update of row r-1 (RING: that row is the ring row, not
+    // stored); FIRST_UPD: row r-1 is the first owned row (no y-speed below
+    // it yet, south boundary speed instead).
+    auto row = [&](RowCarry& c, const Raw& cur, int r, auto do_x, auto do_upd, auto ring,
+                   auto first_upd) {
+        const Cell P = project<CL>(M, cur.h, cur.hu, cur.hv, cur.z, cur.ag);
+        double dXh = 0, dXm = 0, dXt = 0, dXz = 0;
+        unsigned eXn = 0;
+        if (do_x.value) {
+            Flux X;
+            const unsigned e = iface_flux(side_x(P), next_side_x(P), M.g, X);
+            dXh = X.Fh - dpp<DPP_PREV>(X.Fh);
+            dXm = X.FhuL - dpp<DPP_PREV>(X.FhuR);
+            dXt = X.Fht - dpp<DPP_PREV>(X.Fht);
+            dXz = X.Fz - dpp<DPP_PREV>(X.Fz);
+            eXn = e | dpp_u<DPP_PREV>(e);
+        }
+        Flux Y;
+        const Side Ls{c.h, c.tau, c.v, c.u, c.Pi, c.z, c.qy, c.by2, c.aK, c.inv};
+        const unsigned eY = iface_flux(Ls, side_y(P), M.g, Y);
+        if (do_upd.value) {
+            const int ru = r - 1;
+            double hn = c.h - lx * c.dXh - ly * (Y.Fh - c.Yh);
+            double hun = c.hu - lx * c.dXm - ly * (Y.Fht - c.Yt);
+            double hvn = c.hv - lx * c.dXt - ly * (Y.FhuL - c.YR);
+            double zn = c.z - lx * c.dXz - ly * (Y.Fz - c.Yz);
             if (M.momentum_friction) apply_friction(M, st.dt, hn, hun, hvn);
-            const bool owned_row = ru < jend;
-            if (owned_row && owned_lane) {
-                const unsigned e = check_state(hn, hun, hvn, zn) | eXp | eXl | eYp | eY;
+            if (!ring.value && owned_lane) {
+                const unsigned e = check_state(hn, hun, hvn, zn) | c.eX | c.eY | eY;
                 if (e) record_error(ctrl, e, n);
                 store_cell(M, D, (long long)ru * M.nx + col, hn, hun, hvn, zn);
             }
-            if (speeds) {
-                // new states of ghost cells at non-periodic edges
-                if (!owned_row && yghost_n) {
-                    hn = nh; hun = nhu; hvn = nhv; zn = nz;
-                    ghost_from(M, BCN, hn, hun, hvn);
-                }
-                if (xghost_e) {
-                    const double a = shup(hn), b = shup(hun), c = shup(hvn), d = shup(zn);
+            if (SPEEDS) {
+                if (xghost_e) {                      // ring lane is the east ghost
+                    const double a = dpp<DPP_PREV>(hn), b = dpp<DPP_PREV>(hun);
+                    const double cc = dpp<DPP_PREV>(hvn), d = dpp<DPP_PREV>(zn);
                     if (lane == l_ring) {
-                        hn = a; hun = b; hvn = c; zn = d;
+                        hn = a; hun = b; hvn = cc; zn = d;
                         ghost_from(M, BCE, hn, hun, hvn);
                     }
                 }
-                if (xghost_w) {
-                    const double a = shdn(hn), b = shdn(hun), c = shdn(hvn), d = shdn(zn);
+                if (xghost_w) {                      // lane 0 is the west ghost
+                    const double a = dpp<DPP_NEXT>(hn), b = dpp<DPP_NEXT>(hun);
+                    const double cc = dpp<DPP_NEXT>(hvn), d = dpp<DPP_NEXT>(zn);
                     if (lane == 0) {
-                        hn = a; hun = b; hvn = c; zn = d;
+                        hn = a; hun = b; hvn = cc; zn = d;
                         ghost_from(M, BCW, hn, hun, hvn);
                     }
                 }
-                // A_g of (col, ru) as fetched with the row: ghosts copy the
-                // adjacent interior cell's value, as the boundary rule says
-                const Cell PN = project(M, hn, hun, hvn, zn, agp);
-                const Side nxt = shfl_speed_x_next(PN);
-                if (owned_row && (owned_lane || (lane == 0 && xghost_w)))
-                    sx = fmax(sx, iface_speed(side_x(PN), nxt, M.g));
-                if (ru - 1 >= j0 && ru - 1 < jend && owned_lane)
-                    sy = fmax(sy, iface_speed(Np, side_y(PN), M.g));
-                if (ru == j0 && yghost_s && owned_lane) {
-                    double gh = hn, ghu = hun, ghv = hvn;
-                    ghost_from(M, BCS, gh, ghu, ghv);
-                    const Cell G = project(M, gh, ghu, ghv, zn, agp);
-                    sy = fmax(sy, iface_speed(side_y(G), side_y(PN), M.g));
+                Side Ny;
+                if (ring.value && yghost_n) {        // north ghost row of the new state
+                    Ny = ghost_side_y<CL>(M, BCN, c.N, c.ag);
+                } else {
+                    const Cell PN = project<CL>(M, hn, hun, hvn, zn, c.ag);
+                    Ny = side_y(PN);
+                    if (!ring.value) {
+                        const Side Nx = side_x(PN);
+                        const Side nb = next_speed_side(Nx);
+                        const double s = iface_speed(Nx, nb, M.g);
+                        if (owned_lane || (lane == 0 && xghost_w)) sx = fmax(sx, s);
+                    }
                 }
-                Np = side_y(PN);
-                nh = hn; nhu = hun; nhv = hvn; nz = zn;
+                if (!first_upd.value) {
+                    const double s = iface_speed(c.N, Ny, M.g);
+                    if (owned_lane) sy = fmax(sy, s);
+                } else if (yghost_s) {
+                    const double s = iface_speed(ghost_side_y<CL>(M, BCS, Ny, c.ag), Ny, M.g);
+                    if (owned_lane) sy = fmax(sy, s);
+                }
+                c.N = Ny;
             }
         }
-        Pp = P;
-        agp = ag;
-        Xp = X;
-        Yp = Y;
-        eXp = eX;
-        eYp = eY;
+        c.h = P.h; c.tau = P.tau; c.u = P.u; c.v = P.v; c.Pi = P.Pi; c.z = P.z; c.qy = P.qy;
+        c.by2 = P.by2; c.aK = P.aK; c.inv = P.inv_aK; c.hu = P.hu; c.hv = P.hv; c.ag = cur.ag;
+        c.dXh = dXh; c.dXm = dXm; c.dXt = dXt; c.dXz = dXz; c.eX = eXn; c.eY = eY;
+        c.Yh = Y.Fh; c.Yt = Y.Fht; c.YR = Y.FhuR; c.Yz = Y.Fz;
+    };
+    using Y_ = std::true_type;
+    using N_ = std::false_type;
+
+    // row j0-1: projection only
+    RowCarry c{};
+    {
+        const Raw w = load_row(M, S, Agf, ci, gxin, j0 - 1);
+        const Cell P = project<CL>(M, w.h, w.hu, w.hv, w.z, w.ag);
+        c.h = P.h; c.tau = P.tau; c.u = P.u; c.v = P.v; c.Pi = P.Pi; c.z = P.z; c.qy = P.qy;
+        c.by2 = P.by2; c.aK = P.aK; c.inv = P.inv_aK; c.hu = P.hu; c.hv = P.hv; c.ag = w.ag;
     }
-    if (speeds) {
+    Raw cur = load_row(M, S, Agf, ci, gxin, j0);
+    Raw nxt = load_row(M, S, Agf, ci, gxin, j0 + 1);
+    row(c, cur, j0, Y_{}, N_{}, N_{}, N_{});                       // row j0: fluxes only
+    cur = nxt;
+    if (j0 + 1 < j_ring) {
+        nxt = load_row(M, S, Agf, ci, gxin, j0 + 2);
+        row(c, cur, j0 + 1, Y_{}, Y_{}, N_{}, Y_{});               // update of row j0
+        cur = nxt;
+        for (int r = j0 + 2; r < j_ring; ++r) {                   // owned rows j0+1 .. jend-2
+            nxt = load_row(M, S, Agf, ci, gxin, r + 1);
+            row(c, cur, r, Y_{}, Y_{}, N_{}, N_{});
+            cur = nxt;
+        }
+        nxt = load_row(M, S, Agf, ci, gxin, j_ring + 1);
+        row(c, cur, j_ring, Y_{}, Y_{}, N_{}, N_{});               // update of row jend-1
+    } else {                                                       // one owned row
+        nxt = load_row(M, S, Agf, ci, gxin, j_ring + 1);
+        row(c, cur, j_ring, Y_{}, Y_{}, N_{}, Y_{});
+    }
+    row(c, nxt, j_ring + 1, N_{}, Y_{}, Y_{}, N_{});               // ring row (speeds only)
+    if (SPEEDS) {
         sx = wave_max(sx);
         sy = wave_max(sy);
         if (lane == 0) {
@@ -174,14 +281,21 @@ k_fused(Model M, StateView<T> S, StateView<T> D, const double* __restrict__ Agf,
     }
 }
 
-template <typename T, int TY>
-void launch_fused_ty(const Model& M, StateView<T> S, StateView<T> D, const double* Ag, Ctrl* ctrl,
-                     int n, double cfl, double t_end, double fixed_dt, hipStream_t stream) {
+template <typename T>
+void launch_fused_rows(const Model& M, StateView<T> S, StateView<T> D, const double* Ag,
+                       Ctrl* ctrl, int n, double cfl, double t_end, double fixed_dt, int TY,
+                       hipStream_t stream) {
     const int tiles_x = (M.nx + FUSED_OWN - 1) / FUSED_OWN;
     const int tiles_y = (M.ny + TY - 1) / TY;
     const dim3 grid(tiles_x, (tiles_y + FUSED_WAVES - 1) / FUSED_WAVES);
-    hipLaunchKernelGGL((k_fused<T, TY>), grid, dim3(64 * FUSED_WAVES), 0, stream, M, S, D, Ag,
-                       ctrl, n, cfl, t_end, fixed_dt, tiles_y);
+    const int cl = closure_class(M);
+    const bool sp = !(fixed_dt > 0.0);
+    auto kern = cl == CL_GRASS3 ? (sp ? k_fused<T, CL_GRASS3, true> : k_fused<T, CL_GRASS3, false>)
+              : cl == CL_GRASS1 ? (sp ? k_fused<T, CL_GRASS1, true> : k_fused<T, CL_GRASS1, false>)
+              : cl == CL_GRASSM ? (sp ? k_fused<T, CL_GRASSM, true> : k_fused<T, CL_GRASSM, false>)
+                                : (sp ? k_fused<T, CL_THRESH, true> : k_fused<T, CL_THRESH, false>);
+    hipLaunchKernelGGL(kern, grid, dim3(64 * FUSED_WAVES), 0, stream, M, S, D, Ag, ctrl, n, cfl,
+                       t_end, fixed_dt, TY, tiles_y);
 }
 
 }  // namespace sve

@@ -38,7 +38,7 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
     return r;
 }
 
-template <typename T>
+template <typename T, int CL>
 __global__ void __launch_bounds__(SPEED_BLOCK)
 k_speeds(Model M, StateView<T> S, const double* __restrict__ Agf, Ctrl* ctrl, int slot) {
     __shared__ double sh[2][SPEED_BLOCK / 64];
@@ -51,18 +51,18 @@ k_speeds(Model M, StateView<T> S, const double* __restrict__ Agf, Ctrl* ctrl, in
         const int j = (int)(t / (M.nx + 1)), m = (int)(t % (M.nx + 1));
         double h, hu, hv, z, ag;
         fetch(M, S, Agf, m - 1, j, h, hu, hv, z, ag);
-        const Cell L = project(M, h, hu, hv, z, ag);
+        const Cell L = project<CL>(M, h, hu, hv, z, ag);
         fetch(M, S, Agf, m, j, h, hu, hv, z, ag);
-        const Cell R = project(M, h, hu, hv, z, ag);
+        const Cell R = project<CL>(M, h, hu, hv, z, ag);
         sx = iface_speed(side_x(L), side_x(R), M.g);
     } else if (t < nxi + nyi) {
         const long long u = t - nxi;
         const int i = (int)(u % M.nx), m = (int)(u / M.nx);
         double h, hu, hv, z, ag;
         fetch(M, S, Agf, i, m - 1, h, hu, hv, z, ag);
-        const Cell L = project(M, h, hu, hv, z, ag);
+        const Cell L = project<CL>(M, h, hu, hv, z, ag);
         fetch(M, S, Agf, i, m, h, hu, hv, z, ag);
-        const Cell R = project(M, h, hu, hv, z, ag);
+        const Cell R = project<CL>(M, h, hu, hv, z, ag);
         sy = iface_speed(side_y(L), side_y(R), M.g);
     }
     const double bx = block_max<SPEED_BLOCK>(sx, sh[0]);
@@ -109,7 +109,7 @@ __device__ __forceinline__ void apply_friction(const Model& M, double dt, double
     hv = hv / den;
 }
 
-template <typename T>
+template <typename T, int CL>
 __global__ void __launch_bounds__(UPDATE_BLOCK)
 k_update(Model M, StateView<T> S, StateView<T> D, const double* __restrict__ Agf, Ctrl* ctrl,
          int n, double cfl, double t_end, double fixed_dt) {
@@ -122,11 +122,11 @@ k_update(Model M, StateView<T> S, StateView<T> D, const double* __restrict__ Agf
     const int i = (int)(k % M.nx), j = (int)(k / M.nx);
     double h, hu, hv, z, ag;
     fetch(M, S, Agf, i, j, h, hu, hv, z, ag);
-    const Cell C = project(M, h, hu, hv, z, ag);
+    const Cell C = project<CL>(M, h, hu, hv, z, ag);
     fetch(M, S, Agf, i - 1, j, h, hu, hv, z, ag);
-    const Cell W = project(M, h, hu, hv, z, ag);
+    const Cell W = project<CL>(M, h, hu, hv, z, ag);
     fetch(M, S, Agf, i + 1, j, h, hu, hv, z, ag);
-    const Cell E = project(M, h, hu, hv, z, ag);
+    const Cell E = project<CL>(M, h, hu, hv, z, ag);
     Flux fl, fr;
     unsigned err = iface_flux(side_x(W), side_x(C), M.g, fl);
     err |= iface_flux(side_x(C), side_x(E), M.g, fr);
@@ -134,9 +134,9 @@ k_update(Model M, StateView<T> S, StateView<T> D, const double* __restrict__ Agf
     double hn, hun, hvn, zn;
     if (M.dim == 2) {
         fetch(M, S, Agf, i, j - 1, h, hu, hv, z, ag);
-        const Cell So = project(M, h, hu, hv, z, ag);
+        const Cell So = project<CL>(M, h, hu, hv, z, ag);
         fetch(M, S, Agf, i, j + 1, h, hu, hv, z, ag);
-        const Cell No = project(M, h, hu, hv, z, ag);
+        const Cell No = project<CL>(M, h, hu, hv, z, ag);
         Flux gb, gt;
         err |= iface_flux(side_y(So), side_y(C), M.g, gb);
         err |= iface_flux(side_y(C), side_y(No), M.g, gt);

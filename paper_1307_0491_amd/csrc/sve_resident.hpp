@@ -60,15 +60,16 @@ __device__ __forceinline__ void res_cell(const Model& M, const ResLds& L,
     if (g >= 0 && M.bc_kind[g] == BC_INFLOW) { h = M.bc_h[g]; hu = M.bc_hu[g]; }
 }
 
+template <int CL>
 __device__ __forceinline__ double res_max_speed(const Model& M, const ResLds& L,
                                                 const double* __restrict__ Agf) {
     double s = 0.0;
     for (int m = threadIdx.x; m <= M.nx; m += RES_BLOCK) {
         double h, hu, z, ag;
         res_cell(M, L, Agf, m - 1, h, hu, z, ag);
-        const Cell A = project(M, h, hu, 0.0, z, ag);
+        const Cell A = project<CL>(M, h, hu, 0.0, z, ag);
         res_cell(M, L, Agf, m, h, hu, z, ag);
-        const Cell B = project(M, h, hu, 0.0, z, ag);
+        const Cell B = project<CL>(M, h, hu, 0.0, z, ag);
         s = fmax(s, iface_speed(side_x(A), side_x(B), M.g));
     }
     s = wave_max(s);
@@ -80,7 +81,7 @@ __device__ __forceinline__ double res_max_speed(const Model& M, const ResLds& L,
     return r;
 }
 
-template <typename T>
+template <typename T, int CL>
 __global__ void __launch_bounds__(RES_BLOCK)
 k_resident_1d(Model M, StateView<T> S, StateView<T> D, const double* __restrict__ Agf,
               Ctrl* ctrl, int n0, int nsteps, double cfl, double t_end, double fixed_dt) {
@@ -123,9 +124,9 @@ k_resident_1d(Model M, StateView<T> S, StateView<T> D, const double* __restrict_
         for (int m = threadIdx.x; m <= nx; m += RES_BLOCK) {
             double h, hu, z, ag;
             res_cell(M, L, Agf, m - 1, h, hu, z, ag);
-            const Cell A = project(M, h, hu, 0.0, z, ag);
+            const Cell A = project<CL>(M, h, hu, 0.0, z, ag);
             res_cell(M, L, Agf, m, h, hu, z, ag);
-            const Cell B = project(M, h, hu, 0.0, z, ag);
+            const Cell B = project<CL>(M, h, hu, 0.0, z, ag);
             Flux F;
             e |= iface_flux(side_x(A), side_x(B), M.g, F);
             L.Fh[m] = F.Fh;
@@ -163,7 +164,7 @@ k_resident_1d(Model M, StateView<T> S, StateView<T> D, const double* __restrict_
         __syncthreads();
         t = tnew;
         dt_last = dt;
-        if (cfl_mode) S_next = res_max_speed(M, L, Agf);
+        if (cfl_mode) S_next = res_max_speed<CL>(M, L, Agf);
     }
     // write back the last good state into the buffer the host expects
     const StateView<T>& out = (done & 1) ? D : S;
@@ -210,8 +211,13 @@ void launch_resident(sve_ctx* c, int n, double cfl, double t_end, double fixed_d
     T* b1 = static_cast<T*>(c->buf[dst]);
     S = StateView<T>{b0, b0 + c->pitch, b0 + 2 * c->pitch, b0 + 3 * c->pitch};
     D = StateView<T>{b1, b1 + c->pitch, b1 + 2 * c->pitch, b1 + 3 * c->pitch};
-    hipLaunchKernelGGL(k_resident_1d<T>, dim3(1), dim3(RES_BLOCK), res_lds_bytes(c->M.nx),
-                       c->stream,
+    const size_t lds = res_lds_bytes(c->M.nx);
+    const int cl = closure_class(c->M);
+    auto kern = cl == CL_GRASS3 ? k_resident_1d<T, CL_GRASS3>
+              : cl == CL_GRASS1 ? k_resident_1d<T, CL_GRASS1>
+              : cl == CL_GRASSM ? k_resident_1d<T, CL_GRASSM>
+                                : k_resident_1d<T, CL_THRESH>;
+    hipLaunchKernelGGL(kern, dim3(1), dim3(RES_BLOCK), lds, c->stream,
                        c->M, S, D, (const double*)c->Ag, c->ctrl, (int)c->nsteps, n, cfl, t_end,
                        fixed_dt);
 }
