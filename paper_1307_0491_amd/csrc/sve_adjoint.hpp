@@ -1,0 +1,373 @@
+// sve_adjoint.hpp -- reverse mode of one fixed-dt step (Grass closure).
+//
+// For U^{n+1} = U^n - dt/dx (F^L_{i+1/2} - F^R_{i-1/2}) - dt/dy (...), the
+// adjoint of the fluxes of an interface follows from the adjoint state
+// lambda^{n+1} of its two cells, and the chain rule is taken backwards
+// through the interface solver (sve_device.hpp, iface_flux) and the
+// lambda = 0 projection to the conserved variables and the Grass constant.
+// Branches of the solver (max/min selections, the fan state at x/t = 0)
+// are frozen at their forward values; their derivatives are those of the
+// selected expressions.
+#pragma once
+
+#include "sve_device.hpp"
+
+namespace sve {
+
+// Adjoints of the projected quantities of one side of an interface (normal
+// frame, as in Side).
+struct SideAdj {
+    double h, tau, un, ut, Pi, z, q, b2, aK;
+};
+
+// Adjoints of the projected quantities of a cell (x/y frame, as in Cell).
+struct CellAdj {
+    double h, tau, u, v, Pi, z, qx, qy, bx2, by2, aK;
+};
+
+__device__ __forceinline__ void add_x(CellAdj& c, const SideAdj& s) {
+    c.h += s.h; c.tau += s.tau; c.u += s.un; c.v += s.ut; c.Pi += s.Pi; c.z += s.z;
+    c.qx += s.q; c.bx2 += s.b2; c.aK += s.aK;
+}
+__device__ __forceinline__ void add_y(CellAdj& c, const SideAdj& s) {
+    c.h += s.h; c.tau += s.tau; c.v += s.un; c.u += s.ut; c.Pi += s.Pi; c.z += s.z;
+    c.qy += s.q; c.by2 += s.b2; c.aK += s.aK;
+}
+
+// Reverse of iface_flux: given the adjoints of (F_h, F_hu^L, F_hu^R, F_ht,
+// F_z), accumulate the adjoints of both sides' projected quantities.
+__device__ __forceinline__ void iface_vjp(const Side& L, const Side& R, double g,
+                                          const Flux& Fb, SideAdj& Lb, SideAdj& Rb) {
+    // ---- forward, keeping intermediates -------------------------------
+    const bool hmaxL = L.h >= R.h;
+    const double hmax = hmaxL ? L.h : R.h;
+    const double af2 = g * (hmax * hmax * hmax);
+    const bool afL = L.aK >= R.aK;
+    const double a_f = afL ? L.aK : R.aK;
+    const double inv_af = 1.0 / a_f;
+    const double Hbar = 0.5 * (L.h + R.h);
+    const double gH = g * Hbar;
+    const double dZ = R.z - L.z;
+    const double w = R.Pi - L.Pi + gH * dZ;
+    const double u_est = 0.5 * (L.un + R.un) - w * (0.5 * inv_af);
+    const double hbu = Hbar * u_est;
+    const double fl = B_FLOOR * a_f;
+    const double cand[4] = {L.b2, R.b2, hbu * hbu, fl * fl};
+    int ib = 0;
+    for (int i = 1; i < 4; ++i)
+        if (cand[i] > cand[ib]) ib = i;
+    const double b2 = cand[ib];
+    const double b = sqrt(b2);
+    const double A2 = af2 + b2;
+    const double a = sqrt(A2);
+    const double inv_a = 1.0 / a;
+    const double a2 = a * a;
+    const double apb = a + b;
+    const double c = af2 / apb;
+    const bool tminL = L.tau <= R.tau;
+    const double tmin = tminL ? L.tau : R.tau;
+    const double t3 = tmin * tmin * tmin;
+    const double kappa = Hbar * t3;
+    const double PL = L.Pi + a2 * L.tau;
+    const double PR = R.Pi + a2 * R.tau;
+    const double inv_a2 = 1.0 / a2;
+    const double D = (PR - PL) * inv_a2;
+    const double AL = L.un - a * L.tau;
+    const double AR = R.un + a * R.tau;
+    const double kdz = kappa * dZ;
+    const double num = AR - AL - a * D - c * kdz;
+    const double T0 = num * (0.5 * inv_a);
+    const double bk_a = b * kappa * inv_a;
+    const double eps = c * bk_a;
+    const double s2 = AL + c * T0;
+    const double s4 = AR - c * (T0 + D + kdz);
+    const double B = (s4 - s2) + eps * dZ;
+    const double Cq = (R.q - L.q) - 0.5 * (s4 + s2) * dZ;
+    const double disc = B * B - 8.0 * eps * Cq;
+    const double sq = sqrt(fmax(disc, 0.0));
+    const double den = B + sq;
+    const double zeta = -2.0 * Cq / den + 0.5 * dZ;
+    const double tau1 = T0 - bk_a * zeta;
+    const double tau2 = tau1 + kappa * zeta;
+    const double tau3 = tau2 + D;
+    const double tau4 = tau1 + D + kdz;
+    const double sig2 = AL + c * tau1;
+    const double us = sig2 + b * tau2;
+    const double sig4 = AR - c * tau4;
+    const bool c1 = AL < 0.0, l2 = sig2 < 0.0, l3 = us < 0.0, l4 = sig4 < 0.0, l5 = AR < 0.0;
+    const bool outer = !l2 || l4;
+    const bool right = l3;
+    // outer-state tau source: 0 = tau_L, 1 = tau1, 4 = tau4, 5 = tau_R
+    const int srcO = right ? (l5 ? 5 : 4) : (c1 ? 1 : 0);
+    const double tauO = srcO == 5 ? R.tau : srcO == 4 ? tau4 : srcO == 1 ? tau1 : L.tau;
+    const double sa = right ? -a : a;
+    const double Aside = right ? AR : AL;
+    const double Pside = right ? PR : PL;
+    const double uO = Aside + sa * tauO;
+    const double PiO = Pside - a2 * tauO;
+    const double tauM = l3 ? tau3 : tau2;
+    const double PiM = PL - a2 * tau2;
+    const double tau0 = outer ? tauO : tauM;
+    const double u0 = outer ? uO : us;
+    const double Pi0 = outer ? PiO : PiM;
+    const double Z0 = outer ? (right ? R.z : L.z) : L.z + zeta;
+    const double vt0 = right ? R.ut : L.ut;
+    const double Fh = u0 / tau0;
+
+    // ---- reverse ------------------------------------------------------
+    Lb = SideAdj{0, 0, 0, 0, 0, 0, 0, 0, 0};
+    Rb = SideAdj{0, 0, 0, 0, 0, 0, 0, 0, 0};
+    // F_hu^{L,R} = P0 + gH (Z0 - z_{L,R}), F_ht = F_h vt0, F_z = O0
+    const double P0b = Fb.FhuL + Fb.FhuR;
+    double gHb = Fb.FhuL * (Z0 - L.z) + Fb.FhuR * (Z0 - R.z);
+    const double Z0b = gH * (Fb.FhuL + Fb.FhuR);
+    Lb.z -= gH * Fb.FhuL;
+    Rb.z -= gH * Fb.FhuR;
+    const double O0b = Fb.Fz;
+    double Fhb = Fb.Fh + Fb.Fht * vt0;
+    const double vt0b = Fb.Fht * Fh;
+    if (right) Rb.ut += vt0b; else Lb.ut += vt0b;
+    // P0 = u0 F_h + Pi0
+    double u0b = P0b * Fh;
+    Fhb += P0b * u0;
+    const double Pi0b = P0b;
+    // F_h = u0 / tau0
+    u0b += Fhb / tau0;
+    const double tau0b = -Fhb * Fh / tau0;
+    // fan-state selection
+    double tau1b = 0, tau2b = 0, tau3b = 0, tau4b = 0, zetab = 0, sig2b = 0, usb = 0;
+    double ALb = 0, ARb = 0, PLb = 0, PRb = 0, ab = 0, a2b = 0;
+    if (outer) {
+        double tauOb = tau0b;
+        // uO = Aside + sa tauO
+        if (right) { ARb += u0b; ab -= u0b * tauO; } else { ALb += u0b; ab += u0b * tauO; }
+        tauOb += u0b * sa;
+        // PiO = Pside - a2 tauO
+        if (right) PRb += Pi0b; else PLb += Pi0b;
+        a2b -= Pi0b * tauO;
+        tauOb -= Pi0b * a2;
+        if (srcO == 5) Rb.tau += tauOb;
+        else if (srcO == 4) tau4b += tauOb;
+        else if (srcO == 1) tau1b += tauOb;
+        else Lb.tau += tauOb;
+        if (right) { Rb.z += Z0b; Rb.q += O0b; } else { Lb.z += Z0b; Lb.q += O0b; }
+    } else {
+        if (l3) tau3b += tau0b; else tau2b += tau0b;
+        usb += u0b;
+        PLb += Pi0b;
+        a2b -= Pi0b * tau2;
+        tau2b -= Pi0b * a2;
+        // Z0 = zL + zeta ; O0 = qL + sig2 zeta
+        Lb.z += Z0b;
+        zetab += Z0b;
+        Lb.q += O0b;
+        sig2b += O0b * zeta;
+        zetab += O0b * sig2;
+    }
+    // us = sig2 + b tau2
+    sig2b += usb;
+    double bb = usb * tau2;
+    tau2b += usb * b;
+    // sig2 = AL + c tau1
+    ALb += sig2b;
+    double cb = sig2b * tau1;
+    tau1b += sig2b * c;
+    // tau4 = tau1 + D + kdz ; tau3 = tau2 + D ; tau2 = tau1 + kappa zeta
+    tau1b += tau4b;
+    double Db = tau4b;
+    double kdzb = tau4b;
+    tau2b += tau3b;
+    Db += tau3b;
+    tau1b += tau2b;
+    double kappab = tau2b * zeta;
+    zetab += tau2b * kappa;
+    // tau1 = T0 - bk_a zeta
+    double T0b = tau1b;
+    double bk_ab = -tau1b * zeta;
+    zetab -= tau1b * bk_a;
+    // zeta = -2 Cq / den + dZ/2
+    double Cqb = -2.0 * zetab / den;
+    double denb = 2.0 * zetab * Cq / (den * den);
+    double dZb = 0.5 * zetab;
+    // den = B + sq ; sq = sqrt(disc)
+    double Bb = denb;
+    const double discb = sq > 0.0 ? denb / (2.0 * sq) : 0.0;
+    // disc = B^2 - 8 eps Cq
+    Bb += 2.0 * B * discb;
+    double epsb = -8.0 * Cq * discb;
+    Cqb -= 8.0 * eps * discb;
+    // Cq = (qR - qL) - (s4 + s2) dZ / 2
+    Rb.q += Cqb;
+    Lb.q -= Cqb;
+    double s4b = -0.5 * dZ * Cqb;
+    double s2b = -0.5 * dZ * Cqb;
+    dZb -= 0.5 * (s4 + s2) * Cqb;
+    // B = s4 - s2 + eps dZ
+    s4b += Bb;
+    s2b -= Bb;
+    epsb += Bb * dZ;
+    dZb += Bb * eps;
+    // s4 = AR - c (T0 + D + kdz)
+    ARb += s4b;
+    cb -= s4b * (T0 + D + kdz);
+    T0b -= s4b * c;
+    Db -= s4b * c;
+    kdzb -= s4b * c;
+    // s2 = AL + c T0
+    ALb += s2b;
+    cb += s2b * T0;
+    T0b += s2b * c;
+    // eps = c bk_a
+    cb += epsb * bk_a;
+    bk_ab += epsb * c;
+    // bk_a = b kappa inv_a
+    bb += bk_ab * kappa * inv_a;
+    kappab += bk_ab * b * inv_a;
+    double inv_ab = bk_ab * b * kappa;
+    // T0 = num * inv_a / 2, num = AR - AL - a D - c kdz
+    const double numb = 0.5 * T0b * inv_a;
+    inv_ab += 0.5 * T0b * num;
+    ARb += numb;
+    ALb -= numb;
+    ab -= numb * D;
+    Db -= numb * a;
+    cb -= numb * kdz;
+    kdzb -= numb * c;
+    // kdz = kappa dZ
+    kappab += kdzb * dZ;
+    dZb += kdzb * kappa;
+    // AR = uR + a tauR ; AL = uL - a tauL
+    Rb.un += ARb;
+    ab += ARb * R.tau;
+    Rb.tau += ARb * a;
+    Lb.un += ALb;
+    ab -= ALb * L.tau;
+    Lb.tau -= ALb * a;
+    // D = (PR - PL) / a2
+    PRb += Db * inv_a2;
+    PLb -= Db * inv_a2;
+    a2b -= Db * D * inv_a2;
+    // PR = PiR + a2 tauR ; PL = PiL + a2 tauL
+    Rb.Pi += PRb;
+    a2b += PRb * R.tau;
+    Rb.tau += PRb * a2;
+    Lb.Pi += PLb;
+    a2b += PLb * L.tau;
+    Lb.tau += PLb * a2;
+    // kappa = Hbar tmin^3
+    double Hbarb = kappab * t3;
+    const double tminb = kappab * 3.0 * Hbar * tmin * tmin;
+    if (tminL) Lb.tau += tminb; else Rb.tau += tminb;
+    // c = af2 / (a + b)
+    double af2b = cb / apb;
+    ab -= cb * c / apb;
+    bb -= cb * c / apb;
+    // a2 = a a ; inv_a = 1 / a
+    ab += 2.0 * a * a2b;
+    ab -= inv_ab * inv_a * inv_a;
+    // a = sqrt(A2) ; A2 = af2 + b2 ; b = sqrt(b2)
+    const double A2b = ab / (2.0 * a);
+    af2b += A2b;
+    double b2b = A2b + bb / (2.0 * b);
+    // b2 = max(bL2, bR2, hbu^2, fl^2)
+    double hbub = 0.0, flb = 0.0;
+    if (ib == 0) Lb.b2 += b2b;
+    else if (ib == 1) Rb.b2 += b2b;
+    else if (ib == 2) hbub = 2.0 * hbu * b2b;
+    else flb = 2.0 * fl * b2b;
+    double a_fb = B_FLOOR * flb;
+    // hbu = Hbar u_est
+    Hbarb += hbub * u_est;
+    const double u_estb = hbub * Hbar;
+    // u_est = (uL + uR)/2 - w inv_af / 2
+    Lb.un += 0.5 * u_estb;
+    Rb.un += 0.5 * u_estb;
+    const double wb = -0.5 * u_estb * inv_af;
+    const double inv_afb = -0.5 * u_estb * w;
+    // w = PiR - PiL + gH dZ
+    Rb.Pi += wb;
+    Lb.Pi -= wb;
+    gHb += wb * dZ;
+    dZb += wb * gH;
+    // inv_af = 1 / a_f ; a_f = max(aK)
+    a_fb -= inv_afb * inv_af * inv_af;
+    if (afL) Lb.aK += a_fb; else Rb.aK += a_fb;
+    // dZ = zR - zL
+    Rb.z += dZb;
+    Lb.z -= dZb;
+    // gH = g Hbar ; Hbar = (hL + hR)/2
+    Hbarb += g * gHb;
+    Lb.h += 0.5 * Hbarb;
+    Rb.h += 0.5 * Hbarb;
+    // af2 = g hmax^3
+    const double hmaxb = af2b * 3.0 * g * hmax * hmax;
+    if (hmaxL) Lb.h += hmaxb; else Rb.h += hmaxb;
+}
+
+// Reverse of the projection of a cell with the Grass closure: maps the
+// adjoints of the projected quantities to (h, hu, hv, z_b, A_g).
+__device__ __forceinline__ void project_vjp_grass(const Model& M, double h, double hu, double hv,
+                                                  double Ag, const CellAdj& cb, double& hb,
+                                                  double& hub, double& hvb, double& zb,
+                                                  double& Agb) {
+    const double g = M.g;
+    const double tau = 1.0 / h;
+    const double u = hu * tau, v = hv * tau;
+    const double uu = u * u, vv = v * v, w = uu + vv;
+    const double m = M.mg;
+    // closure values and partial derivatives (q = Ag p (u, v), beta = Ag r N)
+    double p, dp_dw, r, dr_dw;
+    if (M.mg_is3) {
+        p = w; dp_dw = 1.0; r = 1.0; dr_dw = 0.0;
+    } else if (M.mg_is1) {
+        p = 1.0; dp_dw = 0.0; r = w > 0.0 ? 1.0 / w : 0.0; dr_dw = w > 0.0 ? -r / w : 0.0;
+    } else if (w > 0.0) {
+        const double e = 0.5 * (m - 1.0);
+        p = pow(w, e);
+        dp_dw = e * p / w;
+        r = p / w;
+        dr_dw = (e - 1.0) * r / w;
+    } else {
+        p = 0.0; dp_dw = 0.0; r = 0.0; dr_dw = 0.0;
+    }
+    const double Nx = m * uu + vv, Ny = uu + m * vv;
+    double bx, by;
+    if (M.mg_is3) { bx = Ag * (3.0 * uu + vv); by = Ag * (uu + 3.0 * vv); }
+    else if (M.mg_is1) { bx = Ag; by = Ag; }
+    else { bx = Ag * r * Nx; by = Ag * r * Ny; }
+    const double dqx_du = Ag * (p + 2.0 * uu * dp_dw), dqx_dv = Ag * 2.0 * u * v * dp_dw;
+    const double dqy_du = dqx_dv, dqy_dv = Ag * (p + 2.0 * vv * dp_dw);
+    double dbx_du, dbx_dv, dby_du, dby_dv, dbx_dA, dby_dA;
+    if (M.mg_is1) {
+        dbx_du = dbx_dv = dby_du = dby_dv = 0.0;
+        dbx_dA = dby_dA = 1.0;
+    } else {
+        dbx_du = Ag * (dr_dw * 2.0 * u * Nx + r * 2.0 * m * u);
+        dbx_dv = Ag * (dr_dw * 2.0 * v * Nx + r * 2.0 * v);
+        dby_du = Ag * (dr_dw * 2.0 * u * Ny + r * 2.0 * u);
+        dby_dv = Ag * (dr_dw * 2.0 * v * Ny + r * 2.0 * m * v);
+        dbx_dA = M.mg_is3 ? 3.0 * uu + vv : r * Nx;
+        dby_dA = M.mg_is3 ? uu + 3.0 * vv : r * Ny;
+    }
+    // b2 = hu^2 + g h^2 beta
+    const double gh2 = g * h * h;
+    const double bxb = cb.bx2 * gh2, byb = cb.by2 * gh2;
+    hub = 2.0 * hu * cb.bx2;
+    hvb = 2.0 * hv * cb.by2;
+    hb = cb.h + 2.0 * g * h * (bx * cb.bx2 + by * cb.by2);
+    // closure
+    double ub = cb.u + cb.qx * dqx_du + cb.qy * dqy_du + bxb * dbx_du + byb * dby_du;
+    double vb = cb.v + cb.qx * dqx_dv + cb.qy * dqy_dv + bxb * dbx_dv + byb * dby_dv;
+    Agb = cb.qx * p * u + cb.qy * p * v + bxb * dbx_dA + byb * dby_dA;
+    // u = hu tau, v = hv tau
+    hub += ub * tau;
+    hvb += vb * tau;
+    double taub = cb.tau + ub * hu + vb * hv;
+    // Pi = g h^2 / 2 ; aK = h sqrt(g h) ; tau = 1 / h
+    hb += cb.Pi * g * h;
+    hb += cb.aK * 1.5 * sqrt(g * h);
+    hb -= taub * tau * tau;
+    zb = cb.z;
+}
+
+}  // namespace sve

@@ -183,7 +183,7 @@ __global__ void k_store_state(Model M, StateView<T> S, double* h, double* hu, do
     if (z) z[k] = (double)S.z[k];
 }
 
-__global__ void k_reset_ctrl(Ctrl* ctrl, double t0) {
+static __global__ void k_reset_ctrl(Ctrl* ctrl, double t0) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         for (int s = 0; s < 3; ++s) {
             ctrl->smax[s][0] = 0ull;
@@ -196,7 +196,7 @@ __global__ void k_reset_ctrl(Ctrl* ctrl, double t0) {
     }
 }
 
-__global__ void k_clear_slot(Ctrl* ctrl, int slot) {
+static __global__ void k_clear_slot(Ctrl* ctrl, int slot) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         ctrl->smax[slot][0] = 0ull;
         ctrl->smax[slot][1] = 0ull;
