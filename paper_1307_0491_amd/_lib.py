@@ -80,6 +80,15 @@ SIGNATURES = {
     "sve_adj_forward": (I, [P, I, D, I]),
     "sve_adj_backward": (I, [P, P, P, P]),
     "sve_adj_step_vjp": (I, [P, D, P, P, P]),
+    "sve_ens_create": (I, [ctypes.POINTER(P), I, ctypes.POINTER(SveMember),
+                           ctypes.POINTER(SveParams), P]),
+    "sve_ens_step": (I, [P, I, D]),
+    "sve_ens_step_sequential": (I, [P, I, D]),
+    "sve_ens_get": (I, [P, I, P, P, P, P, DP, ctypes.POINTER(LL)]),
+    "sve_ens_autotune": (I, [P, I, D, ctypes.POINTER(I), ctypes.POINTER(I)]),
+    "sve_ens_set_schedule": (I, [P, I, I]),
+    "sve_ens_last_elapsed_ms": (I, [P, DP]),
+    "sve_ens_destroy": (I, [P]),
 }
 
 

@@ -226,8 +226,8 @@ __device__ __forceinline__ void closure(const Model& M, double h, double u,
                 bx = Ag * p * (M.mg * uu + vv) * r;
                 by = Ag * p * (uu + M.mg * vv) * r;
             } else {
-                bx = 0.0;
-                by = 0.0;
+                bx = M.mg_is1 ? Ag : 0.0;
+                by = bx;
             }
         }
         return;

@@ -125,20 +125,16 @@ struct RowCarry {
     Side N;                                                    // y view, new state of row r-2
 };
 
+// One tile of one step, run by one wavefront: tile (tx, ty) owns columns
+// [61 tx, 61 tx + 61) and rows [TY ty, TY ty + TY) (clipped to the grid).
+// tx, ty, TY and `st` must be wave-uniform.
 template <typename T, int CL, bool SPEEDS>
-__global__ void __launch_bounds__(64 * FUSED_WAVES)
-k_fused(Model M, StateView<T> S, StateView<T> D, const double* __restrict__ Agf, Ctrl* ctrl,
-        int n, double cfl, double t_end, double fixed_dt, int TY, int tiles_y) {
-    if (ctrl->err) return;
-    const StepTime st = step_time(M, ctrl, n, cfl, t_end, fixed_dt);
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) step_bookkeeping(ctrl, n, st);
+__device__ __forceinline__ void fused_tile(const Model& M, const StateView<T>& S,
+                                           const StateView<T>& D, const double* __restrict__ Agf,
+                                           Ctrl* ctrl, int n, const StepTime& st, int tx, int ty,
+                                           int TY) {
     const int lane = threadIdx.x & 63;
-    // the wavefront index is uniform: make that visible to the compiler so
-    // that all row bookkeeping stays scalar
-    const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int ty = blockIdx.y * FUSED_WAVES + wid;
-    if (ty >= tiles_y) return;                       // whole wavefront
-    const int i0 = blockIdx.x * FUSED_OWN;
+    const int i0 = tx * FUSED_OWN;
     const int j0 = ty * TY;
     const int col = i0 - 1 + lane;
     const int jend = min(j0 + TY, M.ny);             // owned rows [j0, jend)
@@ -279,6 +275,21 @@ k_fused(Model M, StateView<T> S, StateView<T> D, const double* __restrict__ Agf,
             if (sy > 0.0) atomicMax(&ctrl->smax[(n + 1) % 3][1], double_as_u64(sy));
         }
     }
+}
+
+template <typename T, int CL, bool SPEEDS>
+__global__ void __launch_bounds__(64 * FUSED_WAVES)
+k_fused(Model M, StateView<T> S, StateView<T> D, const double* __restrict__ Agf, Ctrl* ctrl,
+        int n, double cfl, double t_end, double fixed_dt, int TY, int tiles_y) {
+    if (ctrl->err) return;
+    const StepTime st = step_time(M, ctrl, n, cfl, t_end, fixed_dt);
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) step_bookkeeping(ctrl, n, st);
+    // the wavefront index is uniform: make that visible to the compiler so
+    // that all row bookkeeping stays scalar
+    const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int ty = blockIdx.y * FUSED_WAVES + wid;
+    if (ty >= tiles_y) return;                       // whole wavefront
+    fused_tile<T, CL, SPEEDS>(M, S, D, Agf, ctrl, n, st, blockIdx.x, ty, TY);
 }
 
 template <typename T>
