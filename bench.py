@@ -1,15 +1,28 @@
-"""Benchmark of the hot path: explicit FP64 2D steps of the relaxation
-scheme on the periodic 2D Grass dune, 2000 x 2000 cells on [0, 1000]^2 m,
-A_g = 1e-3, m_g = 3, CFL 0.5 (one step = one pass of the whole method:
-projection, interface Riemann solves, update and the CFL reduction of the
-next step).
+"""Benchmark of the hot path on one GPU.
 
-Prints one JSON line (cell-updates/s, HBM roofline of the step kernel, the
-CPU oracle timed on a bounded sample of the same workload).
+Main line: explicit FP64 2D steps of the relaxation scheme on the periodic
+2D Grass dune, 2000 x 2000 cells on [0, 1000]^2 m, A_g = 1e-3, m_g = 3,
+CFL 0.5.  One step is one pass of the whole method (ghosts, projection,
+interface Riemann solves, conservative update and the CFL wave-speed
+reduction for the next step).
+
+Two more legs measure the forms built on the step:
+  * ensemble: 256 periodic Grass dunes of sides drawn from
+    {256, 384, 512, 768, 1024} (A_g log-uniform on [1e-4, 1e-2], m_g uniform
+    on [1, 4], bump amplitude uniform on [0.5, 1]), each with its own CFL dt,
+    advanced in one graph-replayed persistent launch per step, against the
+    same steps run member by member with the single-grid kernel;
+  * adjoint: 1024 x 1024 Grass dune, 2000 fixed-dt steps, loss
+    1/2 |z_b(T) - z_target|^2 with z_target from a run with a smooth +-30 %
+    A_g field; gradients with respect to the initial state and the A_g field
+    with sqrt(N) checkpointing, against the plain forward run.
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,6 +39,22 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak
 BYTES_PER_CELL_FP64 = 64.0     # read h, hu, hv, z_b and write them once (8 B each)
 NX = NY = 2000
 
+# HBM traffic of the fused step kernel on the main workload, from two
+# rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each
+# scaled by the ratio of known bytes to the same counter on a plain device
+# copy.  Valid only for the kernel sources it was taken on (hash below).
+TRAFFIC = None
+
+
+def kernel_source_hash() -> str:
+    d = os.path.join(ROOT, "paper_1307_0491_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hpp", ".hip")):
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
 
 def workload():
     import workloads as W
@@ -36,7 +65,6 @@ def workload():
 def cpu_baseline(nsteps: int = 3):
     """The oracle as it stands, on the host, over `nsteps` steps of the same
     2000 x 2000 grid (bounded sample of the workload)."""
-    os.environ.setdefault("OMP_NUM_THREADS", "1")
     import oracle as O
     h, hu, hv, zb = workload()
     o = O.Oracle2D(h, hu, hv, zb, 1000.0 / NX, 1000.0 / NY,
@@ -50,24 +78,11 @@ def cpu_baseline(nsteps: int = 3):
             "seconds": el}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5000)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--rows", type=int, default=32, help="tile rows of the fused kernel")
-    ap.add_argument("--path", default="fused", choices=["fused", "split"])
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-steps", type=int, default=3)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "multi-GPU sharding is not built", file=sys.stderr)
-        sys.exit(2)
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
-    import torch
-    import paper_1307_0491_amd as sve
-    sve.require_device()
+
+def main_leg(args, sve, torch):
     h, hu, hv, zb = workload()
     p = sve.Params(law=sve.LAW_GRASS, A_g=1e-3, m_g=3.0)
     bcs = [sve.BC(sve.BC_PERIODIC)] * 4
@@ -85,36 +100,205 @@ def main():
     kern_ms = s.last_elapsed_ms()           # HIP events on the launch stream
     (gh, ghu, ghv, gz), t, dtl, ns = s.get_state()
     s.close()
-    cells = NX * NY
-    value = cells * args.steps / wall
-    per_launch_s = kern_ms * 1e-3 / args.steps
-    achieved = BYTES_PER_CELL_FP64 * cells / per_launch_s / 1e9
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "cell-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "2D Grass dune, periodic, 2000x2000 cells on [0,1000]^2 m, "
-                               "A_g=1e-3, m_g=3, CFL 0.5, FP64",
-                   "nx": NX, "ny": NY, "path": args.path, "tile_rows": args.rows,
-                   "sim_time_s": t, "steps_done": ns},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_fused (update of step n + wave speeds of step n+1)",
-                     "bytes_per_cell": BYTES_PER_CELL_FP64,
-                     "avg_launch_us": per_launch_s * 1e6},
-    }
-    if not np.all(np.isfinite(gh)) or not np.all(gh > 0):
-        out["error"] = "non-finite or non-positive depth after the run"
-    if not args.no_cpu:
+    ok = bool(np.all(np.isfinite(gh)) and np.all(gh > 0))
+    return wall, kern_ms, t, ns, ok
+
+
+def copy_calibration(torch, mib: int, reps: int = 5):
+    """Plain streaming kernels of a known size (read 8n bytes, write 8n
+    bytes: an elementwise multiply by one), for scaling the HBM counters."""
+    n = mib * 1024 * 1024 // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    return {"bytes_read": 8 * n, "bytes_written": 8 * n, "reps": reps}
+
+
+def ensemble_leg(args, sve, torch):
+    import workloads as W
+    from paper_1307_0491_amd.ensemble import Ensemble
+    draw = W.ensemble_draw(args.ens_members)
+    members = []
+    cells = 0
+    for m in draw:
+        h, hu, hv, zb, dx, dy = W.ensemble_member_state(m)
+        members.append(dict(h=h, hu=hu, hv=hv, zb=zb, lx=1000.0, ly=1000.0, A_g=m.Ag, m_g=m.mg))
+        cells += m.n * m.n
+    e = Ensemble(members, stream=sve.current_stream_handle())
+    del members
+    rows, mode = e.autotune(3, 0.5)
+    e.step(5, 0.5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e.step(args.ens_steps, 0.5)
+    torch.cuda.synchronize()
+    wall_b = time.perf_counter() - t0
+    ms_b = e.last_elapsed_ms()
+    progress(f"ensemble batched: {args.ens_steps} steps in {wall_b:.3f} s")
+    t0 = time.perf_counter()
+    e.step_sequential(args.ens_seq_steps, 0.5)
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t0
+    ms_s = e.last_elapsed_ms()
+    progress(f"ensemble sequential: {args.ens_seq_steps} steps in {wall_s:.3f} s")
+    e.close()
+    per_b = wall_b / args.ens_steps
+    per_s = wall_s / args.ens_seq_steps
+    sizes = {}
+    for m in draw:
+        sizes[m.n] = sizes.get(m.n, 0) + 1
+    return {"members": len(draw), "cells": cells, "member_sizes": sizes,
+            "schedule": {"tile_rows": rows, "mode": "queue" if mode == 0 else "grid"},
+            "batched": {"steps": args.ens_steps, "ms_per_step": per_b * 1e3,
+                        "kernel_ms_per_step": ms_b / args.ens_steps,
+                        "cell_updates_per_s": cells / per_b},
+            "sequential": {"steps": args.ens_seq_steps, "ms_per_step": per_s * 1e3,
+                           "kernel_ms_per_step": ms_s / args.ens_seq_steps,
+                           "cell_updates_per_s": cells / per_s},
+            "speedup_vs_sequential": per_s / per_b}
+
+
+def adjoint_leg(args, sve, torch):
+    import workloads as W
+    from paper_1307_0491_amd.adjoint import AdjointRun
+    n = args.adj_n
+    h, hu, hv, zb, dx, dy = W.dune2d(n, n)
+    ag_true = W.adjoint_ag_field(n, n)
+    ag0 = np.full((n, n), 1e-3)
+    p = sve.Params(law=sve.LAW_GRASS, A_g=1e-3, m_g=3.0)
+    bcs = [sve.BC(sve.BC_PERIODIC)] * 4
+    stream = sve.current_stream_handle()
+
+    def solver(ag):
+        s = sve.Solver(h, hu, zb, hv, lx=1000.0, ly=1000.0, params=p, bcs=bcs, Ag=ag,
+                       stream=stream)
+        s.set_tile_rows(args.adj_fwd_rows)
+        return s
+
+    s = solver(ag0)
+    s.step(1, 0.5)
+    _, _, dt_cfl, _ = s.get_state()
+    s.close()
+    dt = 0.9 * dt_cfl
+    steps = args.adj_steps
+    s = solver(ag_true)
+    s.step_fixed_dt(steps, dt)
+    z_target = s.get_state_torch()[0][3].clone()
+    s.close()
+    # plain forward at the evaluation point
+    s = solver(ag0)
+    s.step_fixed_dt(5, dt)
+    s.close()
+    s = solver(ag0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step_fixed_dt(steps, dt)
+    torch.cuda.synchronize()
+    fwd = time.perf_counter() - t0
+    s.close()
+    progress(f"adjoint: plain forward {fwd:.3f} s")
+    # forward with checkpoints, then the reverse sweep.  A second gradient on
+    # the same context (over the next window of `steps` steps) reuses the
+    # checkpoint buffers: its time is the steady-state cost of a gradient.
+    s = solver(ag0)
+    run = AdjointRun(s)
+    run.set_tile_rows(args.adj_rows)
+    times = []
+    for it in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run.forward(steps, dt)
+        zT = s.get_state_torch()[0][3]
+        gT = torch.zeros((4, n, n), dtype=torch.float64, device="cuda")
+        gT[3] = zT - z_target
+        g0, gAg = run.backward(gT)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        progress(f"adjoint: forward with checkpoints + backward {times[-1]:.3f} s")
+        if it == 0:
+            loss = 0.5 * float(torch.sum((zT - z_target) ** 2))
+            g_linf = (float(g0[3].abs().max()), float(gAg.abs().max()))
+            finite = bool(torch.isfinite(g0).all() and torch.isfinite(gAg).all())
+    s.close()
+    every = int(np.ceil(np.sqrt(steps)))
+    return {"nx": n, "ny": n, "steps": steps, "dt": dt, "checkpoint_every": every,
+            "tile_rows": {"forward": args.adj_fwd_rows, "reverse": args.adj_rows},
+            "forward_s": fwd, "forward_backward_s": times[-1],
+            "forward_backward_first_s": times[0],
+            "ratio_vs_forward": times[-1] / fwd,
+            "loss": loss, "grad_zb0_linf": g_linf[0], "grad_Ag_linf": g_linf[1],
+            "finite": finite}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--rows", type=int, default=32, help="tile rows of the fused kernel")
+    ap.add_argument("--path", default="fused", choices=["fused", "split"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--legs", default="main,ensemble,adjoint",
+                    help="comma list of main, ensemble, adjoint")
+    ap.add_argument("--ens-members", type=int, default=256)
+    ap.add_argument("--ens-steps", type=int, default=1000)
+    ap.add_argument("--ens-seq-steps", type=int, default=100)
+    ap.add_argument("--adj-n", type=int, default=1024)
+    ap.add_argument("--adj-steps", type=int, default=2000)
+    ap.add_argument("--adj-rows", type=int, default=8, help="tile rows of the reverse kernel")
+    ap.add_argument("--adj-fwd-rows", type=int, default=16,
+                    help="tile rows of the forward kernel in the adjoint leg")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MiB",
+                    help="also run plain device copies of this size (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "multi-GPU sharding is not built", file=sys.stderr)
+        sys.exit(2)
+    legs = set(args.legs.split(","))
+
+    import torch
+    import paper_1307_0491_amd as sve
+    sve.require_device()
+    out = {"metric": METRIC, "value": None, "unit": "cell-updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": None,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "2D Grass dune, periodic, 2000x2000 cells on [0,1000]^2 m, "
+                                  "A_g=1e-3, m_g=3, CFL 0.5, FP64",
+                      "nx": NX, "ny": NY, "path": args.path, "tile_rows": args.rows}}
+    if "main" in legs:
+        wall, kern_ms, t, ns, ok = main_leg(args, sve, torch)
+        progress(f"main: {args.steps} steps in {wall:.3f} s")
+        cells = NX * NY
+        per_launch_s = kern_ms * 1e-3 / args.steps
+        achieved = BYTES_PER_CELL_FP64 * cells / per_launch_s / 1e9
+        src = kernel_source_hash()
+        traffic = None
+        if TRAFFIC is not None and TRAFFIC["src"] == src and args.path == "fused" \
+                and args.rows == TRAFFIC["rows"]:
+            traffic = TRAFFIC["bytes_per_launch"]
+        out["value"] = cells * args.steps / wall
+        out["ms_per_step"] = wall * 1e3 / args.steps
+        out["config"].update({"sim_time_s": t, "steps_done": ns})
+        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                           "kernel": "k_fused (update of step n + wave speeds of step n+1)",
+                           "bytes_per_cell": BYTES_PER_CELL_FP64,
+                           "avg_launch_us": per_launch_s * 1e6, "kernel_src": src}
+        if not ok:
+            out["error"] = "non-finite or non-positive depth after the run"
+    if args.copy_calib:
+        out["copy_calibration"] = copy_calibration(torch, args.copy_calib)
+    if "ensemble" in legs:
+        out["ensemble"] = ensemble_leg(args, sve, torch)
+    if "adjoint" in legs:
+        out["adjoint"] = adjoint_leg(args, sve, torch)
+    if not args.no_cpu and "main" in legs:
+        progress("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     print(json.dumps(out), flush=True)
 

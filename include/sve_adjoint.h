@@ -14,7 +14,9 @@
  * Memory: the forward keeps ceil(n/k) checkpoints of the state and the
  * backward one segment of k states (k = ceil(sqrt(n)) by default), 32 bytes
  * per cell each; all buffers are owned by the context and freed by
- * sve_destroy or the next sve_adj_forward.
+ * sve_destroy or by an sve_adj_forward with another segment layout (a
+ * forward run with the same number of steps and checkpoint interval reuses
+ * them).
  *
  * Device arrays below are caller-owned, on the context's device, read and
  * written on the context's stream; a "state array" is 4*nx*ny doubles
@@ -55,6 +57,13 @@ int sve_adj_backward(sve_ctx *ctx, const double *gT, double *g0, double *gAg);
  */
 int sve_adj_step_vjp(sve_ctx *ctx, double dt, const double *lam_in, double *lam_out,
                      double *gAg);
+
+/*
+ * Tile height (rows per wavefront: 8, 16, 32 or 64; default 8) of the
+ * reverse-step kernel of this context.  Results do not depend on it.
+ * SVE_ERR_ARG for other values.
+ */
+int sve_adj_set_tile_rows(sve_ctx *ctx, int rows);
 
 #ifdef __cplusplus
 }

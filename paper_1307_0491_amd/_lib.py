@@ -7,7 +7,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsve.so")
+# the library built in the package directory, unless SVE_LIBRARY names another build
+LIB_PATH = os.environ.get("SVE_LIBRARY") or os.path.join(HERE, "libsve.so")
 
 # error codes
 SVE_OK = 0
@@ -80,6 +81,7 @@ SIGNATURES = {
     "sve_adj_forward": (I, [P, I, D, I]),
     "sve_adj_backward": (I, [P, P, P, P]),
     "sve_adj_step_vjp": (I, [P, D, P, P, P]),
+    "sve_adj_set_tile_rows": (I, [P, I]),
     "sve_ens_create": (I, [ctypes.POINTER(P), I, ctypes.POINTER(SveMember),
                            ctypes.POINTER(SveParams), P]),
     "sve_ens_step": (I, [P, I, D]),

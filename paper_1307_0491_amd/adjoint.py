@@ -49,6 +49,10 @@ class AdjointRun:
               "sve_adj_backward")
         return g0, gAg
 
+    def set_tile_rows(self, rows: int):
+        """Tile height of the reverse-step kernel (8, 16, 32 or 64)."""
+        check(self.lib.sve_adj_set_tile_rows(self.s.handle, int(rows)), "sve_adj_set_tile_rows")
+
     def step_vjp(self, dt: float, lam):
         """One reverse step at the solver's current state."""
         import torch

@@ -27,84 +27,124 @@ struct sve_adjoint_state {
     int nsteps = 0, every = 0;
     double dt = 0.0;
     std::vector<double*> ckpt;     // state at steps 0, every, 2 every, ... (4 pitch each)
-    double* seg = nullptr;         // `every` states of the current segment
+    double* seg[2] = {nullptr, nullptr};   // `every` states of a segment, two segments
     double* lam[2] = {nullptr, nullptr};
     Ctrl* ctrl = nullptr;          // control block of the recomputation
+    hipStream_t side = nullptr;    // stream of the recomputation
+    hipEvent_t ev_start = nullptr, ev_recomp[2] = {nullptr, nullptr},
+               ev_rev[2] = {nullptr, nullptr};
     bool ready = false;
 };
 
 namespace {
 
-constexpr int ADJ_BLOCK = 256;
-
 StateView<double> view(double* base, long long pitch) {
     return StateView<double>{base, base + pitch, base + 2 * pitch, base + 3 * pitch};
 }
 
-// lambda^n = (dU^{n+1}/dU^n)^T lambda^{n+1}; gAg += (dU^{n+1}/dA_g)^T lambda^{n+1}.
-// One thread per cell: the four interfaces of the cell are solved in reverse
-// and the cell's own share of each is accumulated (periodic grid).
+constexpr int ADJ_WAVES = 4;
+
+struct Lam {
+    double h, hu, hv, z;
+};
+
+__device__ __forceinline__ SideAdj prev_lane(const SideAdj& s) {
+    return SideAdj{dpp<DPP_PREV>(s.h),  dpp<DPP_PREV>(s.tau), dpp<DPP_PREV>(s.un),
+                   dpp<DPP_PREV>(s.ut), dpp<DPP_PREV>(s.Pi),  dpp<DPP_PREV>(s.z),
+                   dpp<DPP_PREV>(s.q),  dpp<DPP_PREV>(s.b2),  dpp<DPP_PREV>(s.aK)};
+}
+
+// lambda^n = (dU^{n+1}/dU^n)^T lambda^{n+1}; gAg += (dU^{n+1}/dA_g)^T lambda^{n+1}
+// on a periodic grid.
+//
+// The tile layout is that of the forward step kernel: one wavefront per
+// tile, lanes 0..63 holding columns i0-1 .. i0+62 (i0 = 61 * tile index,
+// lanes 1..61 owned), marching upward from row j0-1 to row jend.  Every
+// interface the tile needs is solved in reverse once.  At row r, each lane
+// first solves the y-interface (row r-1 | row r), which completes row r-1
+// (then mapped back through the projection and stored) and starts row r;
+// then the x-interface (lane | lane+1) of row r, keeping the left cell's
+// share and passing the right cell's share one lane up (wave_shr:1).  The
+// adjoint seed of an interface's fluxes comes from lambda^{n+1} of its two
+// cells: U' = U - dt/dx (F^L_{i+1/2} - F^R_{i-1/2}) - ...
 template <int CL>
-__global__ void __launch_bounds__(ADJ_BLOCK)
-k_adjoint_step(Model M, StateView<double> U, const double* __restrict__ Agf,
-               StateView<double> Lin, StateView<double> Lout, double* __restrict__ gAg,
-               double dt) {
-    const long long N = (long long)M.nx * M.ny;
-    const long long k = (long long)blockIdx.x * ADJ_BLOCK + threadIdx.x;
-    if (k >= N) return;
-    const int i = (int)(k % M.nx), j = (int)(k / M.nx);
-    const int iw = i == 0 ? M.nx - 1 : i - 1, ie = i == M.nx - 1 ? 0 : i + 1;
-    const int js = j == 0 ? M.ny - 1 : j - 1, jn = j == M.ny - 1 ? 0 : j + 1;
-    const long long kc = k, kw = (long long)j * M.nx + iw, ke = (long long)j * M.nx + ie;
-    const long long ks = (long long)js * M.nx + i, kn = (long long)jn * M.nx + i;
-    auto ag = [&](long long q) { return Agf ? Agf[q] : M.Ag; };
-    auto cell = [&](long long q) {
-        return project<CL>(M, U.h[q], U.hu[q], U.hv[q], U.z[q], ag(q));
-    };
-    const Cell C = cell(kc), W = cell(kw), E = cell(ke), S = cell(ks), No = cell(kn);
+// Two waves per SIMD: the register budget is 256 (a few values spill).
+__global__ void __launch_bounds__(64 * ADJ_WAVES, 2)
+k_adjoint_march(Model M, StateView<double> U, const double* __restrict__ Agf,
+                StateView<double> Lin, StateView<double> Lout, double* __restrict__ gAg,
+                double dt, int TY, int tiles_y) {
+    const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int ty = blockIdx.y * ADJ_WAVES + wid;
+    if (ty >= tiles_y) return;                       // whole wavefront
+    const int lane = threadIdx.x & 63;
+    const int i0 = blockIdx.x * FUSED_OWN;
+    const int j0 = ty * TY;
+    const int jend = min(j0 + TY, M.ny);             // owned rows [j0, jend)
+    const int l_last = min(FUSED_OWN, M.nx - i0);    // owned lanes 1..l_last
+    const bool owned = lane >= 1 && lane <= l_last;
+    const int col = i0 - 1 + lane;
+    const int ci = wrap(col, M.nx);
     const double lx = dt / M.dx, ly = dt / M.dy;
-    auto lam = [&](long long q, double& a, double& b, double& c, double& d) {
-        a = Lin.h[q]; b = Lin.hu[q]; c = Lin.hv[q]; d = Lin.z[q];
+
+    auto load = [&](int r, Cell& P, Lam& l, double& ag) {
+        const long long k = (long long)wrap(r, M.ny) * M.nx + ci;
+        ag = Agf ? Agf[k] : M.Ag;
+        P = project<CL>(M, U.h[k], U.hu[k], U.hv[k], U.z[k], ag);
+        l = Lam{Lin.h[k], Lin.hu[k], Lin.hv[k], Lin.z[k]};
     };
-    double lc_h, lc_u, lc_v, lc_z;
-    lam(kc, lc_h, lc_u, lc_v, lc_z);
+
+    // row r-1, carried: its y view, stored state, A_g, lambda and the
+    // adjoint of its projected quantities gathered so far
+    Side Sp;
+    double hp, hup, hvp, agp;
+    Lam lp;
     CellAdj acc{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    SideAdj Lb, Rb;
-    {   // west interface (W | C): C is the right cell
-        double a, b, c, d;
-        lam(kw, a, b, c, d);
-        const Flux Fb{lx * (lc_h - a), -lx * b, lx * lc_u, lx * (lc_v - c), lx * (lc_z - d)};
-        iface_vjp(side_x(W), side_x(C), M.g, Fb, Lb, Rb);
-        add_x(acc, Rb);
+    {
+        Cell P;
+        load(j0 - 1, P, lp, agp);
+        Sp = side_y(P);
+        hp = P.h; hup = P.hu; hvp = P.hv;
     }
-    {   // east interface (C | E): C is the left cell
-        double a, b, c, d;
-        lam(ke, a, b, c, d);
-        const Flux Fb{lx * (a - lc_h), -lx * lc_u, lx * b, lx * (c - lc_v), lx * (d - lc_z)};
-        iface_vjp(side_x(C), side_x(E), M.g, Fb, Lb, Rb);
-        add_x(acc, Lb);
+    for (int r = j0; r <= jend; ++r) {
+        Cell P;
+        Lam l;
+        double ag;
+        load(r, P, l, ag);
+        CellAdj an{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        {                                            // y-interface (r-1 | r)
+            const Flux Fb{ly * (l.h - lp.h), -ly * lp.hv, ly * l.hv, ly * (l.hu - lp.hu),
+                          ly * (l.z - lp.z)};
+            SideAdj Lb, Rb;
+            iface_vjp(Sp, side_y(P), M.g, Fb, Lb, Rb);
+            if (r > j0) {                            // row r-1 is complete
+                add_y(acc, Lb);
+                double hb, hub, hvb, zb, Agb;
+                project_vjp_grass(M, hp, hup, hvp, agp, acc, hb, hub, hvb, zb, Agb);
+                if (owned) {
+                    const long long k = (long long)(r - 1) * M.nx + col;
+                    Lout.h[k] = lp.h + hb;
+                    Lout.hu[k] = lp.hu + hub;
+                    Lout.hv[k] = lp.hv + hvb;
+                    Lout.z[k] = lp.z + zb;
+                    if (gAg) gAg[k] += Agb;
+                }
+            }
+            add_y(an, Rb);
+        }
+        if (r < jend) {                              // x-interfaces of row r
+            const double rh = dpp<DPP_NEXT>(l.h), ru = dpp<DPP_NEXT>(l.hu);
+            const double rv = dpp<DPP_NEXT>(l.hv), rz = dpp<DPP_NEXT>(l.z);
+            const Flux Fb{lx * (rh - l.h), -lx * l.hu, lx * ru, lx * (rv - l.hv), lx * (rz - l.z)};
+            SideAdj Lb, Rb;
+            iface_vjp(side_x(P), next_side_x(P), M.g, Fb, Lb, Rb);
+            add_x(an, Lb);
+            add_x(an, prev_lane(Rb));
+        }
+        Sp = side_y(P);
+        hp = P.h; hup = P.hu; hvp = P.hv; agp = ag;
+        lp = l;
+        acc = an;
     }
-    {   // south interface (S | C): normal momentum hv, transverse hu
-        double a, b, c, d;
-        lam(ks, a, b, c, d);
-        const Flux Fb{ly * (lc_h - a), -ly * c, ly * lc_v, ly * (lc_u - b), ly * (lc_z - d)};
-        iface_vjp(side_y(S), side_y(C), M.g, Fb, Lb, Rb);
-        add_y(acc, Rb);
-    }
-    {   // north interface (C | N)
-        double a, b, c, d;
-        lam(kn, a, b, c, d);
-        const Flux Fb{ly * (a - lc_h), -ly * lc_v, ly * c, ly * (b - lc_u), ly * (d - lc_z)};
-        iface_vjp(side_y(C), side_y(No), M.g, Fb, Lb, Rb);
-        add_y(acc, Lb);
-    }
-    double hb, hub, hvb, zb, Agb;
-    project_vjp_grass(M, C.h, C.hu, C.hv, ag(kc), acc, hb, hub, hvb, zb, Agb);
-    Lout.h[kc] = lc_h + hb;
-    Lout.hu[kc] = lc_u + hub;
-    Lout.hv[kc] = lc_v + hvb;
-    Lout.z[kc] = lc_z + zb;
-    if (gAg) gAg[kc] += Agb;
 }
 
 __global__ void k_copy4(StateView<double> dst, const double* __restrict__ src, long long N) {
@@ -146,8 +186,10 @@ void free_adj(sve_adjoint_state* a) {
     for (double* p : a->ckpt)
         if (p) (void)hipFree(p);
     a->ckpt.clear();
-    if (a->seg) (void)hipFree(a->seg);
-    a->seg = nullptr;
+    for (int i = 0; i < 2; ++i) {
+        if (a->seg[i]) (void)hipFree(a->seg[i]);
+        a->seg[i] = nullptr;
+    }
     for (int i = 0; i < 2; ++i) {
         if (a->lam[i]) (void)hipFree(a->lam[i]);
         a->lam[i] = nullptr;
@@ -158,18 +200,64 @@ void free_adj(sve_adjoint_state* a) {
 }
 
 // One fixed-dt step from `src` to `dst` with the fused kernel.
-void fwd_step(sve_ctx* c, Ctrl* ctrl, double* src, double* dst, int n, double dt) {
+void fwd_step(sve_ctx* c, Ctrl* ctrl, double* src, double* dst, int n, double dt,
+              hipStream_t stream) {
     launch_fused_rows<double>(c->M, view(src, c->pitch), view(dst, c->pitch), c->Ag, ctrl, n, 0.0,
-                              0.0, dt, c->fused_ty, c->stream);
+                              0.0, dt, c->fused_ty, stream);
+}
+
+// Stream and events of the pipelined backward sweep, created once.
+int ensure_sync(sve_adjoint_state* a) {
+    if (a->side) return SVE_OK;
+    bool ok = hipStreamCreateWithFlags(&a->side, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&a->ev_start, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; i < 2 && ok; ++i)
+        ok = hipEventCreateWithFlags(&a->ev_recomp[i], hipEventDisableTiming) == hipSuccess &&
+             hipEventCreateWithFlags(&a->ev_rev[i], hipEventDisableTiming) == hipSuccess;
+    return ok ? SVE_OK : SVE_ERR_HIP;
+}
+
+void release_sync(sve_adjoint_state* a) {
+    if (a->side) {
+        (void)hipStreamSynchronize(a->side);
+        (void)hipStreamDestroy(a->side);
+        a->side = nullptr;
+    }
+    hipEvent_t* evs[5] = {&a->ev_start, &a->ev_recomp[0], &a->ev_recomp[1], &a->ev_rev[0],
+                          &a->ev_rev[1]};
+    for (hipEvent_t* e : evs) {
+        if (*e) (void)hipEventDestroy(*e);
+        *e = nullptr;
+    }
+}
+
+// Recompute the states of segment `sgi` into segment buffer `b`, on the
+// side stream.
+void recompute_segment(sve_ctx* ctx, sve_adjoint_state* a, int sgi, int b, int& step_id) {
+    const long long P = ctx->pitch;
+    const size_t bytes = 4 * (size_t)P * sizeof(double);
+    const int s0 = sgi * a->every;
+    const int s1 = std::min(s0 + a->every, a->nsteps);
+    (void)hipMemcpyAsync(a->seg[b], a->ckpt[sgi], bytes, hipMemcpyDeviceToDevice, a->side);
+    for (int s = s0 + 1; s < s1; ++s) {
+        double* src = a->seg[b] + (size_t)(s - 1 - s0) * 4 * P;
+        double* dst = a->seg[b] + (size_t)(s - s0) * 4 * P;
+        fwd_step(ctx, a->ctrl, src, dst, step_id++, a->dt, a->side);
+    }
 }
 
 int reverse_step(sve_ctx* c, double* U, double* lin, double* lout, double* gAg, double dt) {
     const int cl = closure_class(c->M);
-    auto kern = cl == CL_GRASS3 ? k_adjoint_step<CL_GRASS3>
-              : cl == CL_GRASS1 ? k_adjoint_step<CL_GRASS1>
-                                : k_adjoint_step<CL_GRASSM>;
-    hipLaunchKernelGGL(kern, dim3(blocks_for(c->N, ADJ_BLOCK)), dim3(ADJ_BLOCK), 0, c->stream, c->M, view(U, c->pitch), (const double*)c->Ag,
-                       view(lin, c->pitch), view(lout, c->pitch), gAg, dt);
+    auto kern = cl == CL_GRASS3 ? k_adjoint_march<CL_GRASS3>
+              : cl == CL_GRASS1 ? k_adjoint_march<CL_GRASS1>
+                                : k_adjoint_march<CL_GRASSM>;
+    const int TY = c->adj_ty;
+    const int tiles_x = (c->M.nx + FUSED_OWN - 1) / FUSED_OWN;
+    const int tiles_y = (c->M.ny + TY - 1) / TY;
+    const dim3 grid(tiles_x, (tiles_y + ADJ_WAVES - 1) / ADJ_WAVES);
+    hipLaunchKernelGGL(kern, grid, dim3(64 * ADJ_WAVES), 0, c->stream, c->M, view(U, c->pitch),
+                       (const double*)c->Ag, view(lin, c->pitch), view(lout, c->pitch), gAg, dt,
+                       TY, tiles_y);
     return hipGetLastError() == hipSuccess ? SVE_OK : SVE_ERR_HIP;
 }
 
@@ -177,6 +265,7 @@ int reverse_step(sve_ctx* c, double* U, double* lin, double* lout, double* gAg, 
 
 void sve_adjoint_release(sve_ctx* ctx) {
     if (!ctx || !ctx->adj) return;
+    release_sync(ctx->adj);
     free_adj(ctx->adj);
     delete ctx->adj;
     ctx->adj = nullptr;
@@ -194,18 +283,27 @@ int sve_adj_forward(sve_ctx* ctx, int nsteps, double dt, int every) {
     if (!ctx->adj) ctx->adj = new (std::nothrow) sve_adjoint_state();
     if (!ctx->adj) return SVE_ERR_HIP;
     sve_adjoint_state* a = ctx->adj;
-    free_adj(a);
     const size_t bytes = 4 * (size_t)ctx->pitch * sizeof(double);
     const int nck = (nsteps + every - 1) / every;
-    a->ckpt.assign(nck, nullptr);
-    bool ok = true;
-    for (int s = 0; s < nck && ok; ++s) ok = hipMalloc((void**)&a->ckpt[s], bytes) == hipSuccess;
-    ok = ok && hipMalloc((void**)&a->seg, (size_t)every * bytes) == hipSuccess;
-    ok = ok && hipMalloc((void**)&a->ctrl, sizeof(Ctrl)) == hipSuccess;
-    if (!ok) {
+    // buffers of an earlier run with the same segment layout are reused
+    const bool reuse =
+        (int)a->ckpt.size() == nck && a->every == every && a->seg[0] && a->seg[1] && a->ctrl;
+    a->ready = false;
+    if (!reuse) {
         free_adj(a);
-        return SVE_ERR_HIP;
+        a->ckpt.assign(nck, nullptr);
+        bool ok = true;
+        for (int s = 0; s < nck && ok; ++s)
+            ok = hipMalloc((void**)&a->ckpt[s], bytes) == hipSuccess;
+        for (int i = 0; i < 2; ++i)
+            ok = ok && hipMalloc((void**)&a->seg[i], (size_t)every * bytes) == hipSuccess;
+        ok = ok && hipMalloc((void**)&a->ctrl, sizeof(Ctrl)) == hipSuccess;
+        if (!ok) {
+            free_adj(a);
+            return SVE_ERR_HIP;
+        }
     }
+    a->every = every;
     hipLaunchKernelGGL(k_reset_ctrl, dim3(1), dim3(64), 0, ctx->stream, a->ctrl, 0.0);
     // checkpoints are taken from the context's own stepping, one segment
     // per call (one stream synchronisation per segment)
@@ -238,26 +336,41 @@ int sve_adj_backward(sve_ctx* ctx, const double* gT, double* g0, double* gAg) {
                        view(a->lam[0], P), gT, N);
     if (gAg)
         hipLaunchKernelGGL(k_zero, dim3(blocks_for(N, 256)), dim3(256), 0, ctx->stream, gAg, N);
+    if (ensure_sync(a)) return SVE_ERR_HIP;
+    // Segments are swept last to first.  The recomputation of segment k-1
+    // (side stream, segment buffer (k-1)&1) does not depend on the reverse
+    // steps of segment k (context stream, buffer k&1), so the two overlap;
+    // events order each buffer's reuse.
     int cur = 0;
     const int nck = (int)a->ckpt.size();
     int step_id = 0;
     hipLaunchKernelGGL(k_reset_ctrl, dim3(1), dim3(64), 0, ctx->stream, a->ctrl, 0.0);
+    if (hipEventRecord(a->ev_start, ctx->stream) != hipSuccess ||
+        hipStreamWaitEvent(a->side, a->ev_start, 0) != hipSuccess)
+        return SVE_ERR_HIP;
+    recompute_segment(ctx, a, nck - 1, (nck - 1) & 1, step_id);
+    (void)hipEventRecord(a->ev_recomp[(nck - 1) & 1], a->side);
     for (int sgi = nck - 1; sgi >= 0; --sgi) {
+        const int b = sgi & 1;
+        if (sgi > 0) {
+            // buffer b^1 was last read by the reverse steps of segment sgi+1
+            if (sgi + 1 < nck) (void)hipStreamWaitEvent(a->side, a->ev_rev[b ^ 1], 0);
+            recompute_segment(ctx, a, sgi - 1, b ^ 1, step_id);
+            (void)hipEventRecord(a->ev_recomp[b ^ 1], a->side);
+        }
+        (void)hipStreamWaitEvent(ctx->stream, a->ev_recomp[b], 0);
         const int s0 = sgi * a->every;
         const int s1 = std::min(s0 + a->every, a->nsteps);
-        // recompute states s0 .. s1-1 into the segment buffer
-        (void)hipMemcpyAsync(a->seg, a->ckpt[sgi], bytes, hipMemcpyDeviceToDevice, ctx->stream);
-        for (int s = s0 + 1; s < s1; ++s) {
-            double* src = a->seg + (size_t)(s - 1 - s0) * 4 * P;
-            double* dst = a->seg + (size_t)(s - s0) * 4 * P;
-            fwd_step(ctx, a->ctrl, src, dst, step_id++, a->dt);
-        }
         for (int s = s1 - 1; s >= s0; --s) {
-            double* U = a->seg + (size_t)(s - s0) * 4 * P;
+            double* U = a->seg[b] + (size_t)(s - s0) * 4 * P;
             const int rc = reverse_step(ctx, U, a->lam[cur], a->lam[cur ^ 1], gAg, a->dt);
-            if (rc) return rc;
+            if (rc) {
+                (void)hipStreamSynchronize(a->side);
+                return rc;
+            }
             cur ^= 1;
         }
+        (void)hipEventRecord(a->ev_rev[b], ctx->stream);
     }
     hipLaunchKernelGGL(k_copy4_out, dim3(blocks_for(N, 256)), dim3(256), 0, ctx->stream, g0,
                        view(a->lam[cur], P), N);
@@ -291,6 +404,12 @@ int sve_adj_step_vjp(sve_ctx* ctx, double dt, const double* lam_in, double* lam_
     hipLaunchKernelGGL(k_copy4_out, dim3(blocks_for(N, 256)), dim3(256), 0, ctx->stream, lam_out,
                        view(a->lam[1], P), N);
     return hipStreamSynchronize(ctx->stream) == hipSuccess ? SVE_OK : SVE_ERR_HIP;
+}
+
+int sve_adj_set_tile_rows(sve_ctx* ctx, int rows) {
+    if (!ctx || (rows != 8 && rows != 16 && rows != 32 && rows != 64)) return SVE_ERR_ARG;
+    ctx->adj_ty = rows;
+    return SVE_OK;
 }
 
 }  // extern "C"

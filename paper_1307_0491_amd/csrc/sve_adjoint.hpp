@@ -35,16 +35,19 @@ __device__ __forceinline__ void add_y(CellAdj& c, const SideAdj& s) {
 }
 
 // Reverse of iface_flux: given the adjoints of (F_h, F_hu^L, F_hu^R, F_ht,
-// F_z), accumulate the adjoints of both sides' projected quantities.
+// F_z), accumulate the adjoints of both sides' projected quantities.  The
+// forward part repeats iface_flux operation for operation (the same
+// reciprocal and square-root helpers), so every branch is taken exactly as
+// in the forward step; the reverse part needs five more reciprocals.
 __device__ __forceinline__ void iface_vjp(const Side& L, const Side& R, double g,
                                           const Flux& Fb, SideAdj& Lb, SideAdj& Rb) {
     // ---- forward, keeping intermediates -------------------------------
     const bool hmaxL = L.h >= R.h;
-    const double hmax = hmaxL ? L.h : R.h;
+    const double hmax = fmax(L.h, R.h);
     const double af2 = g * (hmax * hmax * hmax);
     const bool afL = L.aK >= R.aK;
-    const double a_f = afL ? L.aK : R.aK;
-    const double inv_af = 1.0 / a_f;
+    const double inv_af = fmin(L.inv_aK, R.inv_aK);
+    const double a_f = fmax(L.aK, R.aK);
     const double Hbar = 0.5 * (L.h + R.h);
     const double gH = g * Hbar;
     const double dZ = R.z - L.z;
@@ -52,26 +55,26 @@ __device__ __forceinline__ void iface_vjp(const Side& L, const Side& R, double g
     const double u_est = 0.5 * (L.un + R.un) - w * (0.5 * inv_af);
     const double hbu = Hbar * u_est;
     const double fl = B_FLOOR * a_f;
-    const double cand[4] = {L.b2, R.b2, hbu * hbu, fl * fl};
-    int ib = 0;
-    for (int i = 1; i < 4; ++i)
-        if (cand[i] > cand[ib]) ib = i;
-    const double b2 = cand[ib];
-    const double b = sqrt(b2);
+    // b^2 = max(bL^2, bR^2, hbu^2, fl^2); ib names the maximum
+    const double m01 = fmax(L.b2, R.b2), m23 = fmax(hbu * hbu, fl * fl);
+    const double b2 = fmax(m01, m23);
+    const int ib = m01 >= m23 ? (L.b2 >= R.b2 ? 0 : 1) : (hbu * hbu >= fl * fl ? 2 : 3);
+    const double b = fsqrt(b2);
     const double A2 = af2 + b2;
-    const double a = sqrt(A2);
-    const double inv_a = 1.0 / a;
+    const double inv_a = frsq(A2);
+    const double a = A2 * inv_a;
     const double a2 = a * a;
     const double apb = a + b;
-    const double c = af2 / apb;
+    const double c = fdiv(af2, apb);
     const bool tminL = L.tau <= R.tau;
-    const double tmin = tminL ? L.tau : R.tau;
+    const double tmin = fmin(L.tau, R.tau);
     const double t3 = tmin * tmin * tmin;
     const double kappa = Hbar * t3;
     const double PL = L.Pi + a2 * L.tau;
     const double PR = R.Pi + a2 * R.tau;
-    const double inv_a2 = 1.0 / a2;
-    const double D = (PR - PL) * inv_a2;
+    const double ia2 = inv_a * inv_a;
+    const double dP = PR - PL;
+    const double D = dP * ia2;
     const double AL = L.un - a * L.tau;
     const double AR = R.un + a * R.tau;
     const double kdz = kappa * dZ;
@@ -84,9 +87,10 @@ __device__ __forceinline__ void iface_vjp(const Side& L, const Side& R, double g
     const double B = (s4 - s2) + eps * dZ;
     const double Cq = (R.q - L.q) - 0.5 * (s4 + s2) * dZ;
     const double disc = B * B - 8.0 * eps * Cq;
-    const double sq = sqrt(fmax(disc, 0.0));
+    const double sq = fsqrt(fmax(disc, 1e-300));
     const double den = B + sq;
-    const double zeta = -2.0 * Cq / den + 0.5 * dZ;
+    const double zq = fdiv(-2.0 * Cq, den);
+    const double zeta = zq + 0.5 * dZ;
     const double tau1 = T0 - bk_a * zeta;
     const double tau2 = tau1 + kappa * zeta;
     const double tau3 = tau2 + D;
@@ -99,20 +103,17 @@ __device__ __forceinline__ void iface_vjp(const Side& L, const Side& R, double g
     const bool right = l3;
     // outer-state tau source: 0 = tau_L, 1 = tau1, 4 = tau4, 5 = tau_R
     const int srcO = right ? (l5 ? 5 : 4) : (c1 ? 1 : 0);
-    const double tauO = srcO == 5 ? R.tau : srcO == 4 ? tau4 : srcO == 1 ? tau1 : L.tau;
-    const double sa = right ? -a : a;
-    const double Aside = right ? AR : AL;
-    const double Pside = right ? PR : PL;
-    const double uO = Aside + sa * tauO;
-    const double PiO = Pside - a2 * tauO;
+    const double tauO = right ? (l5 ? R.tau : tau4) : (c1 ? tau1 : L.tau);
+    const double uO = __builtin_fma(right ? -a : a, tauO, right ? AR : AL);
+    const double PiO = __builtin_fma(-a2, tauO, right ? PR : PL);
     const double tauM = l3 ? tau3 : tau2;
-    const double PiM = PL - a2 * tau2;
+    const double PiM = __builtin_fma(-a2, tau2, PL);
     const double tau0 = outer ? tauO : tauM;
     const double u0 = outer ? uO : us;
     const double Pi0 = outer ? PiO : PiM;
     const double Z0 = outer ? (right ? R.z : L.z) : L.z + zeta;
     const double vt0 = right ? R.ut : L.ut;
-    const double Fh = u0 / tau0;
+    const double Fh = fdiv(u0, tau0);
 
     // ---- reverse ------------------------------------------------------
     Lb = SideAdj{0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -132,8 +133,9 @@ __device__ __forceinline__ void iface_vjp(const Side& L, const Side& R, double g
     Fhb += P0b * u0;
     const double Pi0b = P0b;
     // F_h = u0 / tau0
-    u0b += Fhb / tau0;
-    const double tau0b = -Fhb * Fh / tau0;
+    const double inv_tau0 = frcp(tau0);
+    u0b += Fhb * inv_tau0;
+    const double tau0b = -Fhb * Fh * inv_tau0;
     // fan-state selection
     double tau1b = 0, tau2b = 0, tau3b = 0, tau4b = 0, zetab = 0, sig2b = 0, usb = 0;
     double ALb = 0, ARb = 0, PLb = 0, PRb = 0, ab = 0, a2b = 0;
@@ -141,7 +143,7 @@ __device__ __forceinline__ void iface_vjp(const Side& L, const Side& R, double g
         double tauOb = tau0b;
         // uO = Aside + sa tauO
         if (right) { ARb += u0b; ab -= u0b * tauO; } else { ALb += u0b; ab += u0b * tauO; }
-        tauOb += u0b * sa;
+        tauOb += u0b * (right ? -a : a);
         // PiO = Pside - a2 tauO
         if (right) PRb += Pi0b; else PLb += Pi0b;
         a2b -= Pi0b * tauO;
@@ -185,13 +187,14 @@ __device__ __forceinline__ void iface_vjp(const Side& L, const Side& R, double g
     double T0b = tau1b;
     double bk_ab = -tau1b * zeta;
     zetab -= tau1b * bk_a;
-    // zeta = -2 Cq / den + dZ/2
-    double Cqb = -2.0 * zetab / den;
-    double denb = 2.0 * zetab * Cq / (den * den);
+    // zeta = zq + dZ/2, zq = -2 Cq / den
+    const double inv_den = frcp(den);
+    double Cqb = -2.0 * zetab * inv_den;
+    double denb = -zetab * zq * inv_den;
     double dZb = 0.5 * zetab;
     // den = B + sq ; sq = sqrt(disc)
     double Bb = denb;
-    const double discb = sq > 0.0 ? denb / (2.0 * sq) : 0.0;
+    const double discb = disc > 0.0 ? 0.5 * denb * frcp(sq) : 0.0;
     // disc = B^2 - 8 eps Cq
     Bb += 2.0 * B * discb;
     double epsb = -8.0 * Cq * discb;
@@ -200,7 +203,7 @@ __device__ __forceinline__ void iface_vjp(const Side& L, const Side& R, double g
     Rb.q += Cqb;
     Lb.q -= Cqb;
     double s4b = -0.5 * dZ * Cqb;
-    double s2b = -0.5 * dZ * Cqb;
+    double s2b = s4b;
     dZb -= 0.5 * (s4 + s2) * Cqb;
     // B = s4 - s2 + eps dZ
     s4b += Bb;
@@ -224,7 +227,7 @@ __device__ __forceinline__ void iface_vjp(const Side& L, const Side& R, double g
     bb += bk_ab * kappa * inv_a;
     kappab += bk_ab * b * inv_a;
     double inv_ab = bk_ab * b * kappa;
-    // T0 = num * inv_a / 2, num = AR - AL - a D - c kdz
+    // T0 = num inv_a / 2, num = AR - AL - a D - c kdz
     const double numb = 0.5 * T0b * inv_a;
     inv_ab += 0.5 * T0b * num;
     ARb += numb;
@@ -243,10 +246,10 @@ __device__ __forceinline__ void iface_vjp(const Side& L, const Side& R, double g
     Lb.un += ALb;
     ab -= ALb * L.tau;
     Lb.tau -= ALb * a;
-    // D = (PR - PL) / a2
-    PRb += Db * inv_a2;
-    PLb -= Db * inv_a2;
-    a2b -= Db * D * inv_a2;
+    // D = (PR - PL) inv_a^2
+    PRb += Db * ia2;
+    PLb -= Db * ia2;
+    inv_ab += 2.0 * Db * dP * inv_a;
     // PR = PiR + a2 tauR ; PL = PiL + a2 tauL
     Rb.Pi += PRb;
     a2b += PRb * R.tau;
@@ -259,16 +262,18 @@ __device__ __forceinline__ void iface_vjp(const Side& L, const Side& R, double g
     const double tminb = kappab * 3.0 * Hbar * tmin * tmin;
     if (tminL) Lb.tau += tminb; else Rb.tau += tminb;
     // c = af2 / (a + b)
-    double af2b = cb / apb;
-    ab -= cb * c / apb;
-    bb -= cb * c / apb;
+    const double inv_apb = frcp(apb);
+    double af2b = cb * inv_apb;
+    const double capb = cb * c * inv_apb;
+    ab -= capb;
+    bb -= capb;
     // a2 = a a ; inv_a = 1 / a
     ab += 2.0 * a * a2b;
-    ab -= inv_ab * inv_a * inv_a;
+    ab -= inv_ab * ia2;
     // a = sqrt(A2) ; A2 = af2 + b2 ; b = sqrt(b2)
-    const double A2b = ab / (2.0 * a);
+    const double A2b = 0.5 * ab * inv_a;
     af2b += A2b;
-    double b2b = A2b + bb / (2.0 * b);
+    double b2b = A2b + 0.5 * bb * frcp(b);
     // b2 = max(bL2, bR2, hbu^2, fl^2)
     double hbub = 0.0, flb = 0.0;
     if (ib == 0) Lb.b2 += b2b;

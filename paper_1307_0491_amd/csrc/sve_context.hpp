@@ -25,6 +25,7 @@ struct sve_ctx {
     double t = 0.0, dt_last = 0.0;
     int path = SVE_PATH_FUSED;
     int fused_ty = 32;          // tile rows of the fused kernel
+    int adj_ty = 8;             // tile rows of the reverse-step kernel
     int sticky = SVE_OK;
     bool speeds_valid = false;  // slot nsteps%3 holds the speeds of the state
     double last_ms = 0.0;

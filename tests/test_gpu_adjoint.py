@@ -80,7 +80,12 @@ def test_one_step_dot_product(sve, mg):
     s.close()
 
 
-def test_checkpointed_sweep_dot_product(sve):
+# every: 4 -> 4 segments (the last one short), 5 -> 3 segments (odd count,
+# the pipelined sweep ends on the other segment buffer), 15 -> one segment,
+# 1 -> one state per segment.  rows: tile height of the reverse kernel
+# (20 rows: ragged last tile at 8, one partial tile at 32).
+@pytest.mark.parametrize("every,rows", [(4, 8), (5, 16), (15, 32), (1, 8)])
+def test_checkpointed_sweep_dot_product(sve, every, rows):
     import torch
     from paper_1307_0491_amd.adjoint import AdjointRun
     ny, nx = 20, 24
@@ -88,7 +93,8 @@ def test_checkpointed_sweep_dot_product(sve):
     s, po = make_solver(sve, (h, hu, hv, z), Ag, lx, ly, 3.0)
     dt, nsteps = 0.02, 15
     run = AdjointRun(s)
-    run.forward(nsteps, dt, every=4)                 # 4 segments, the last one short
+    run.set_tile_rows(rows)
+    run.forward(nsteps, dt, every=every)
     rng = np.random.default_rng(8)
     w = rng.standard_normal((4, ny, nx))
     v = rng.standard_normal((4, ny, nx))
@@ -106,6 +112,35 @@ def test_checkpointed_sweep_dot_product(sve):
     o.step_fixed_dt(nsteps, dt)
     assert ns == nsteps
     assert np.max(np.abs(gz - o.z)) <= 1e-12 * np.max(np.abs(o.z))
+    s.close()
+
+
+def test_second_gradient_reuses_buffers(sve):
+    """Two forward/backward pairs on one context (the second reuses the
+    checkpoint buffers, from the state the first left): both transpose the
+    oracle's tangent of their own window."""
+    import torch
+    from paper_1307_0491_amd.adjoint import AdjointRun
+    ny, nx = 18, 30
+    h, hu, hv, z, Ag, lx, ly = random_state(ny, nx, 4)
+    s, po = make_solver(sve, (h, hu, hv, z), Ag, lx, ly, 3.0)
+    dt, nsteps = 0.02, 9
+    run = AdjointRun(s)
+    rng = np.random.default_rng(10)
+    for window in range(2):
+        (sh, shu, shv, sz), _, _, _ = s.get_state()
+        run.forward(nsteps, dt)
+        w = rng.standard_normal((4, ny, nx))
+        v = rng.standard_normal((4, ny, nx))
+        dA = 1e-3 * rng.standard_normal((ny, nx))
+        g0, gAg = run.backward(torch.tensor(w, device="cuda"))
+        g0, gAg = g0.cpu().numpy(), gAg.cpu().numpy()
+        Jv = oracle_tangent((sh, shu, shv, sz), Ag, tuple(v), dA, nsteps, dt, lx / nx, ly / ny,
+                            po)
+        lhs = np.sum(g0 * v) + np.sum(gAg * dA)
+        rhs = sum(np.sum(wi * jv) for wi, jv in zip(w, Jv))
+        scale = np.sum(np.abs(g0 * v)) + np.sum(np.abs(gAg * dA))
+        assert abs(lhs - rhs) <= 1e-11 * scale, (window, lhs, rhs)
     s.close()
 
 
