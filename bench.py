@@ -237,7 +237,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--rows", type=int, default=32, help="tile rows of the fused kernel")
+    ap.add_argument("--rows", type=int, default=0,
+                    help="tile rows of the fused kernel (0: automatic)")
     ap.add_argument("--path", default="fused", choices=["fused", "split"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=3)
@@ -248,8 +249,9 @@ def main():
     ap.add_argument("--ens-seq-steps", type=int, default=100)
     ap.add_argument("--adj-n", type=int, default=1024)
     ap.add_argument("--adj-steps", type=int, default=2000)
-    ap.add_argument("--adj-rows", type=int, default=8, help="tile rows of the reverse kernel")
-    ap.add_argument("--adj-fwd-rows", type=int, default=16,
+    ap.add_argument("--adj-rows", type=int, default=0,
+                    help="tile rows of the reverse kernel (0: automatic)")
+    ap.add_argument("--adj-fwd-rows", type=int, default=0,
                     help="tile rows of the forward kernel in the adjoint leg")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MiB",
                     help="also run plain device copies of this size (counter calibration)")

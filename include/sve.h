@@ -166,10 +166,14 @@ const char *sve_strerror(int code);
 int sve_set_path(sve_ctx *ctx, int path);
 
 /*
- * Rows per tile of the fused 2D kernel (8, 16, 32 or 64; default 32).  Each
- * wavefront owns 61 columns x `rows` rows and recomputes one row and one
- * column around them, so larger tiles cost less redundant work but give
- * fewer wavefronts.
+ * Rows per tile of the fused 2D kernel: 1..65536, or 0 (the default) for an
+ * automatic split.  Each wavefront owns 61 columns x about `rows` rows
+ * (tile heights differ by at most one) and recomputes one row and one
+ * column around them, so taller tiles cost less redundant work but give
+ * fewer wavefronts.  The automatic split makes the tiles as short as keeps
+ * every wavefront of a step resident on the device at once (two per SIMD),
+ * with at least 8 rows each.  Results do not depend on it.  SVE_ERR_ARG for
+ * values outside that range.
  */
 int sve_set_tile_rows(sve_ctx *ctx, int rows);
 

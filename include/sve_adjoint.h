@@ -59,9 +59,10 @@ int sve_adj_step_vjp(sve_ctx *ctx, double dt, const double *lam_in, double *lam_
                      double *gAg);
 
 /*
- * Tile height (rows per wavefront: 8, 16, 32 or 64; default 8) of the
- * reverse-step kernel of this context.  Results do not depend on it.
- * SVE_ERR_ARG for other values.
+ * Tile height (rows per wavefront, 1..65536, or 0 for the automatic split
+ * described at sve_set_tile_rows; default 0) of the reverse-step kernel of
+ * this context.  Results do not depend on it.  SVE_ERR_ARG for other
+ * values.
  */
 int sve_adj_set_tile_rows(sve_ctx *ctx, int rows);
 

@@ -53,7 +53,8 @@ int sve_ens_step(sve_ens *ens, int nsteps, double cfl);
 
 /*
  * Reference schedule: the same steps, member after member, with the
- * single-grid kernel of sve_step (one launch per step per member).
+ * single-grid kernel of sve_step and its default (automatic) tiling, one
+ * launch per step per member.
  */
 int sve_ens_step_sequential(sve_ens *ens, int nsteps, double cfl);
 

@@ -42,8 +42,6 @@ StateView<double> view(double* base, long long pitch) {
     return StateView<double>{base, base + pitch, base + 2 * pitch, base + 3 * pitch};
 }
 
-constexpr int ADJ_WAVES = 4;
-
 struct Lam {
     double h, hu, hv, z;
 };
@@ -67,19 +65,19 @@ __device__ __forceinline__ SideAdj prev_lane(const SideAdj& s) {
 // share and passing the right cell's share one lane up (wave_shr:1).  The
 // adjoint seed of an interface's fluxes comes from lambda^{n+1} of its two
 // cells: U' = U - dt/dx (F^L_{i+1/2} - F^R_{i-1/2}) - ...
+//
+// One wavefront per workgroup, two per SIMD (the register budget is 256; a
+// few values spill).  Workgroup (tx, ty) runs tile (tx, ty) of a split of
+// the rows into tiles_y tiles (tile_rows).
 template <int CL>
-// Two waves per SIMD: the register budget is 256 (a few values spill).
-__global__ void __launch_bounds__(64 * ADJ_WAVES, 2)
+__global__ void __launch_bounds__(64, 2)
 k_adjoint_march(Model M, StateView<double> U, const double* __restrict__ Agf,
                 StateView<double> Lin, StateView<double> Lout, double* __restrict__ gAg,
-                double dt, int TY, int tiles_y) {
-    const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int ty = blockIdx.y * ADJ_WAVES + wid;
-    if (ty >= tiles_y) return;                       // whole wavefront
+                double dt, int tiles_y) {
     const int lane = threadIdx.x & 63;
     const int i0 = blockIdx.x * FUSED_OWN;
-    const int j0 = ty * TY;
-    const int jend = min(j0 + TY, M.ny);             // owned rows [j0, jend)
+    int j0, jend;                                    // owned rows [j0, jend)
+    tile_rows(M.ny, tiles_y, blockIdx.y, j0, jend);
     const int l_last = min(FUSED_OWN, M.nx - i0);    // owned lanes 1..l_last
     const bool owned = lane >= 1 && lane <= l_last;
     const int col = i0 - 1 + lane;
@@ -203,7 +201,8 @@ void free_adj(sve_adjoint_state* a) {
 void fwd_step(sve_ctx* c, Ctrl* ctrl, double* src, double* dst, int n, double dt,
               hipStream_t stream) {
     launch_fused_rows<double>(c->M, view(src, c->pitch), view(dst, c->pitch), c->Ag, ctrl, n, 0.0,
-                              0.0, dt, c->fused_ty, stream);
+                              0.0, dt, fused_tiles_y(c->M.nx, c->M.ny, c->fused_ty, c->wave_slots),
+                              stream);
 }
 
 // Stream and events of the pipelined backward sweep, created once.
@@ -251,13 +250,11 @@ int reverse_step(sve_ctx* c, double* U, double* lin, double* lout, double* gAg, 
     auto kern = cl == CL_GRASS3 ? k_adjoint_march<CL_GRASS3>
               : cl == CL_GRASS1 ? k_adjoint_march<CL_GRASS1>
                                 : k_adjoint_march<CL_GRASSM>;
-    const int TY = c->adj_ty;
     const int tiles_x = (c->M.nx + FUSED_OWN - 1) / FUSED_OWN;
-    const int tiles_y = (c->M.ny + TY - 1) / TY;
-    const dim3 grid(tiles_x, (tiles_y + ADJ_WAVES - 1) / ADJ_WAVES);
-    hipLaunchKernelGGL(kern, grid, dim3(64 * ADJ_WAVES), 0, c->stream, c->M, view(U, c->pitch),
-                       (const double*)c->Ag, view(lin, c->pitch), view(lout, c->pitch), gAg, dt,
-                       TY, tiles_y);
+    const int tiles_y = fused_tiles_y(c->M.nx, c->M.ny, c->adj_ty, c->wave_slots);
+    hipLaunchKernelGGL(kern, dim3(tiles_x, tiles_y), dim3(64), 0, c->stream, c->M,
+                       view(U, c->pitch), (const double*)c->Ag, view(lin, c->pitch),
+                       view(lout, c->pitch), gAg, dt, tiles_y);
     return hipGetLastError() == hipSuccess ? SVE_OK : SVE_ERR_HIP;
 }
 
@@ -407,7 +404,7 @@ int sve_adj_step_vjp(sve_ctx* ctx, double dt, const double* lam_in, double* lam_
 }
 
 int sve_adj_set_tile_rows(sve_ctx* ctx, int rows) {
-    if (!ctx || (rows != 8 && rows != 16 && rows != 32 && rows != 64)) return SVE_ERR_ARG;
+    if (!ctx || rows < 0 || rows > 65536) return SVE_ERR_ARG;
     ctx->adj_ty = rows;
     return SVE_OK;
 }

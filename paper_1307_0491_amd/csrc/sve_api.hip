@@ -168,7 +168,8 @@ template <typename T>
 void launch_fused(sve_ctx* c, int src, int dst, int n, double cfl, double t_end,
                   double fixed_dt) {
     launch_fused_rows<T>(c->M, view_of<T>(c, src), view_of<T>(c, dst), c->Ag, c->ctrl, n, cfl,
-                         t_end, fixed_dt, c->fused_ty, c->stream);
+                         t_end, fixed_dt,
+                         fused_tiles_y(c->M.nx, c->M.ny, c->fused_ty, c->wave_slots), c->stream);
 }
 
 template <typename T>
@@ -276,6 +277,14 @@ int init_impl(sve_ctx** out, int nx, int ny, double Lx, double Ly, const double*
     c->M = make_model(nx, ny, Lx, Ly, dim, p, bc);
     c->storage = storage;
     c->stream = (hipStream_t)stream;
+    {
+        int dev_id = 0, cus = 0;
+        if (hipGetDevice(&dev_id) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id) ==
+                hipSuccess &&
+            cus > 0)
+            c->wave_slots = cus * 4 * FUSED_WAVES_PER_SIMD;   // 4 SIMDs per compute unit
+    }
     c->N = (long long)nx * ny;
     c->pitch = round_up(c->N, 64);
     const size_t esz = storage == SVE_FP32 ? sizeof(float) : sizeof(double);
@@ -452,7 +461,7 @@ int sve_set_path(sve_ctx* ctx, int path) {
 }
 
 int sve_set_tile_rows(sve_ctx* ctx, int rows) {
-    if (!ctx || (rows != 8 && rows != 16 && rows != 32 && rows != 64)) return SVE_ERR_ARG;
+    if (!ctx || rows < 0 || rows > 65536) return SVE_ERR_ARG;
     ctx->fused_ty = rows;
     return SVE_OK;
 }

@@ -24,8 +24,9 @@ struct sve_ctx {
     long long nsteps = 0;
     double t = 0.0, dt_last = 0.0;
     int path = SVE_PATH_FUSED;
-    int fused_ty = 32;          // tile rows of the fused kernel
-    int adj_ty = 8;             // tile rows of the reverse-step kernel
+    int fused_ty = 0;           // tile rows of the fused kernel (0: automatic)
+    int adj_ty = 0;             // tile rows of the reverse-step kernel (0: automatic)
+    int wave_slots = 2048;      // resident wavefronts of the step kernels on the device
     int sticky = SVE_OK;
     bool speeds_valid = false;  // slot nsteps%3 holds the speeds of the state
     double last_ms = 0.0;

@@ -38,7 +38,7 @@ struct EnsTile {
     int m, tx, ty, pad;
 };
 
-constexpr int ENS_WAVES = FUSED_WAVES;
+constexpr int ENS_WAVES = 4;
 
 __host__ __device__ inline StateView<double> view(double* base, long long pitch) {
     return StateView<double>{base, base + pitch, base + 2 * pitch, base + 3 * pitch};
@@ -53,7 +53,9 @@ __device__ __forceinline__ void ens_tile(const EnsMember* __restrict__ mem, cons
     if (t.tx == 0 && t.ty == 0 && (threadIdx.x & 63) == 0) step_bookkeeping(ctrl, n, st);
     const StateView<double> S = view(E.buf[n & 1], E.pitch);
     const StateView<double> D = view(E.buf[(n + 1) & 1], E.pitch);
-    fused_tile<double, CL_GRASSM, true>(E.M, S, D, nullptr, ctrl, n, st, t.tx, t.ty, TY);
+    const int j0 = t.ty * TY;
+    fused_tile<double, CL_GRASSM, true>(E.M, S, D, nullptr, ctrl, n, st, t.tx, j0,
+                                        min(j0 + TY, E.M.ny));
 }
 
 // Persistent wavefronts: pull tiles until the list is exhausted (every
@@ -126,6 +128,7 @@ struct sve_ens {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double last_ms = 0.0;
     int queue_blocks = 512;
+    int wave_slots = 2048;     // resident wavefronts of the single-grid step kernel
     std::vector<int> fail_step;          // per member, -1 when healthy
     int sticky = SVE_OK;
 };
@@ -319,6 +322,7 @@ int sve_ens_create(sve_ens** out, int n, const sve_member* members, const sve_pa
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     e->queue_blocks = 2 * cus;                       // two resident workgroups per CU
+    e->wave_slots = cus * 4 * FUSED_WAVES_PER_SIMD;
     ok = ok && hipStreamSynchronize(e->stream) == hipSuccess && hipGetLastError() == hipSuccess;
     if (!ok || build_tiles(e, e->rows) != SVE_OK) {
         free_ens(e);
@@ -376,7 +380,8 @@ int sve_ens_step_sequential(sve_ens* e, int nsteps, double cfl) {
             const int n = n0 + s;
             launch_fused_rows<double>(E.M, view(E.buf[n & 1], E.pitch),
                                       view(E.buf[(n + 1) & 1], E.pitch), nullptr, E.ctrl, n, cfl,
-                                      0.0, 0.0, e->rows, e->stream);
+                                      0.0, 0.0, fused_tiles_y(E.M.nx, E.M.ny, 0, e->wave_slots),
+                                      e->stream);
         }
     }
     hipLaunchKernelGGL(k_ens_advance, dim3(1), dim3(64), 0, e->stream, e->dbase, nsteps);

@@ -25,7 +25,27 @@
 namespace sve {
 
 constexpr int FUSED_OWN = 61;
-constexpr int FUSED_WAVES = 4;
+constexpr int FUSED_WAVES_PER_SIMD = 2;   // occupancy the step kernel is built for
+constexpr int FUSED_MIN_ROWS = 8;         // shortest tile of the automatic split
+
+// Rows [j0, jend) of tile ty when ny rows are split into T tiles whose
+// heights differ by at most one.
+__host__ __device__ __forceinline__ void tile_rows(int ny, int T, int ty, int& j0, int& jend) {
+    j0 = (int)((long long)ty * ny / T);
+    jend = (int)((long long)(ty + 1) * ny / T);
+}
+
+// Number of row tiles: ceil(ny / rows) for an explicit tile height, else
+// (rows == 0) as many as keep every wavefront of the launch resident at
+// once (tiles_x * T <= wave slots of the device), with tiles of at least
+// FUSED_MIN_ROWS rows.
+inline int fused_tiles_y(int nx, int ny, int rows, int wave_slots) {
+    if (rows > 0) return (ny + rows - 1) / rows;
+    const int tiles_x = (nx + FUSED_OWN - 1) / FUSED_OWN;
+    int T = wave_slots / tiles_x;
+    T = T < ny / FUSED_MIN_ROWS ? T : ny / FUSED_MIN_ROWS;
+    return T < 1 ? 1 : T;
+}
 constexpr int DPP_NEXT = 0x130;   // wave_shl:1 -- lane i reads lane i+1
 constexpr int DPP_PREV = 0x138;   // wave_shr:1 -- lane i reads lane i-1
 
@@ -125,19 +145,17 @@ struct RowCarry {
     Side N;                                                    // y view, new state of row r-2
 };
 
-// One tile of one step, run by one wavefront: tile (tx, ty) owns columns
-// [61 tx, 61 tx + 61) and rows [TY ty, TY ty + TY) (clipped to the grid).
-// tx, ty, TY and `st` must be wave-uniform.
+// One tile of one step, run by one wavefront: tile tx owns columns
+// [61 tx, 61 tx + 61) (clipped to the grid) and rows [j0, jend), jend > j0.
+// tx, j0, jend and `st` must be wave-uniform.
 template <typename T, int CL, bool SPEEDS>
 __device__ __forceinline__ void fused_tile(const Model& M, const StateView<T>& S,
                                            const StateView<T>& D, const double* __restrict__ Agf,
-                                           Ctrl* ctrl, int n, const StepTime& st, int tx, int ty,
-                                           int TY) {
+                                           Ctrl* ctrl, int n, const StepTime& st, int tx, int j0,
+                                           int jend) {
     const int lane = threadIdx.x & 63;
     const int i0 = tx * FUSED_OWN;
-    const int j0 = ty * TY;
     const int col = i0 - 1 + lane;
-    const int jend = min(j0 + TY, M.ny);             // owned rows [j0, jend)
     const int j_ring = jend;
     const int l_last = min(FUSED_OWN, M.nx - i0);    // owned lanes 1..l_last
     const bool owned_lane = lane >= 1 && lane <= l_last;
@@ -277,36 +295,35 @@ __device__ __forceinline__ void fused_tile(const Model& M, const StateView<T>& S
     }
 }
 
+// One wavefront per workgroup: workgroup (tx, ty) runs tile (tx, ty) of a
+// split of the rows into tiles_y tiles (tile_rows).
 template <typename T, int CL, bool SPEEDS>
-__global__ void __launch_bounds__(64 * FUSED_WAVES)
+__global__ void __launch_bounds__(64, FUSED_WAVES_PER_SIMD)
 k_fused(Model M, StateView<T> S, StateView<T> D, const double* __restrict__ Agf, Ctrl* ctrl,
-        int n, double cfl, double t_end, double fixed_dt, int TY, int tiles_y) {
+        int n, double cfl, double t_end, double fixed_dt, int tiles_y) {
     if (ctrl->err) return;
     const StepTime st = step_time(M, ctrl, n, cfl, t_end, fixed_dt);
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) step_bookkeeping(ctrl, n, st);
-    // the wavefront index is uniform: make that visible to the compiler so
-    // that all row bookkeeping stays scalar
-    const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int ty = blockIdx.y * FUSED_WAVES + wid;
-    if (ty >= tiles_y) return;                       // whole wavefront
-    fused_tile<T, CL, SPEEDS>(M, S, D, Agf, ctrl, n, st, blockIdx.x, ty, TY);
+    int j0, jend;
+    tile_rows(M.ny, tiles_y, blockIdx.y, j0, jend);
+    fused_tile<T, CL, SPEEDS>(M, S, D, Agf, ctrl, n, st, blockIdx.x, j0, jend);
 }
 
+// tiles_y: number of row tiles (fused_tiles_y), 1 <= tiles_y <= ny.
 template <typename T>
 void launch_fused_rows(const Model& M, StateView<T> S, StateView<T> D, const double* Ag,
-                       Ctrl* ctrl, int n, double cfl, double t_end, double fixed_dt, int TY,
+                       Ctrl* ctrl, int n, double cfl, double t_end, double fixed_dt, int tiles_y,
                        hipStream_t stream) {
     const int tiles_x = (M.nx + FUSED_OWN - 1) / FUSED_OWN;
-    const int tiles_y = (M.ny + TY - 1) / TY;
-    const dim3 grid(tiles_x, (tiles_y + FUSED_WAVES - 1) / FUSED_WAVES);
+    const dim3 grid(tiles_x, tiles_y);
     const int cl = closure_class(M);
     const bool sp = !(fixed_dt > 0.0);
     auto kern = cl == CL_GRASS3 ? (sp ? k_fused<T, CL_GRASS3, true> : k_fused<T, CL_GRASS3, false>)
               : cl == CL_GRASS1 ? (sp ? k_fused<T, CL_GRASS1, true> : k_fused<T, CL_GRASS1, false>)
               : cl == CL_GRASSM ? (sp ? k_fused<T, CL_GRASSM, true> : k_fused<T, CL_GRASSM, false>)
                                 : (sp ? k_fused<T, CL_THRESH, true> : k_fused<T, CL_THRESH, false>);
-    hipLaunchKernelGGL(kern, grid, dim3(64 * FUSED_WAVES), 0, stream, M, S, D, Ag, ctrl, n, cfl,
-                       t_end, fixed_dt, TY, tiles_y);
+    hipLaunchKernelGGL(kern, grid, dim3(64), 0, stream, M, S, D, Ag, ctrl, n, cfl, t_end,
+                       fixed_dt, tiles_y);
 }
 
 }  // namespace sve

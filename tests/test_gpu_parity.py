@@ -80,10 +80,23 @@ def test_dune2d_periodic_fp64(sve, path):
     assert_fields_close(f, o.state, TOL64)
 
 
-@pytest.mark.parametrize("rows", [8, 16, 64])
+# rows: one-row tiles, uneven splits (75 rows in tiles of 5 and 8 rows, or
+# of 16 with a short last tile), one tile taller than the grid, automatic
+@pytest.mark.parametrize("rows", [1, 5, 8, 16, 64, 100, 0])
 def test_fused_tile_rows_agree(sve, rows):
     case = dune2d_case(130, 75)
     f, t, dtl, ns, o = run_pair(sve, case, grass(sve, Ag=0.05), per(sve), 30, rows=rows)
+    assert t == pytest.approx(o.t, rel=TOL64)
+    assert_fields_close(f, o.state, TOL64)
+
+
+@pytest.mark.parametrize("rows", [1, 3, 0])
+def test_fused_tile_rows_open_boundaries(sve, rows):
+    """Tiles touching inflow and free boundaries, with uneven splits."""
+    case = mpm_case(160, 70)
+    bcs = [sve.BC(sve.BC_INFLOW, 0.5, 2.0, 0.0), sve.BC(sve.BC_FREE),
+           sve.BC(sve.BC_FREE), sve.BC(sve.BC_FREE)]
+    f, t, dtl, ns, o = run_pair(sve, case, mpm(sve), bcs, 40, rows=rows)
     assert t == pytest.approx(o.t, rel=TOL64)
     assert_fields_close(f, o.state, TOL64)
 
