@@ -41,9 +41,14 @@ NX = NY = 2000
 
 # HBM traffic of the fused step kernel on the main workload, from two
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each
-# scaled by the ratio of known bytes to the same counter on a plain device
-# copy.  Valid only for the kernel sources it was taken on (hash below).
-TRAFFIC = None
+# scaled by the ratio of known bytes to the same counter on a plain
+# streaming kernel (1 GiB read, 1 GiB written): FETCH_SIZE x 2.0000,
+# WRITE_SIZE x 1.0000.  Valid only for the kernel sources it was taken on
+# (hash of the HIP sources) and the automatic tile split; otherwise the bench
+# reports null.  Summary: profiles/k_fused_dune2000_fp64_hbm_traffic.md.
+TRAFFIC = {"src": "978d9950cca58c61", "rows": 0,
+           "fetch_kib": 88282.9, "write_kib": 131127.9,
+           "bytes_per_launch": 315.07e6}
 
 
 def kernel_source_hash() -> str:
@@ -288,6 +293,9 @@ def main():
         out["config"].update({"sim_time_s": t, "steps_done": ns})
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                           "traffic_unit": "HBM bytes per launch",
+                           "traffic_vs_algorithmic": (traffic / (BYTES_PER_CELL_FP64 * cells)
+                                                      if traffic else None),
                            "kernel": "k_fused (update of step n + wave speeds of step n+1)",
                            "bytes_per_cell": BYTES_PER_CELL_FP64,
                            "avg_launch_us": per_launch_s * 1e6, "kernel_src": src}
