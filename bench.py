@@ -93,7 +93,8 @@ def main_leg(args, sve, torch):
     bcs = [sve.BC(sve.BC_PERIODIC)] * 4
     stream = sve.current_stream_handle()
     s = sve.Solver(h, hu, zb, hv, lx=1000.0, ly=1000.0, params=p, bcs=bcs, stream=stream)
-    s.set_path(sve.PATH_FUSED if args.path == "fused" else sve.PATH_SPLIT)
+    s.set_path({"fused": sve.PATH_FUSED, "split": sve.PATH_SPLIT,
+                "residual": sve.PATH_RESIDUAL}[args.path])
     s.set_tile_rows(args.rows)
     if args.warmup:
         s.step(args.warmup, 0.5)
@@ -244,7 +245,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--rows", type=int, default=0,
                     help="tile rows of the fused kernel (0: automatic)")
-    ap.add_argument("--path", default="fused", choices=["fused", "split"])
+    ap.add_argument("--path", default="fused", choices=["fused", "split", "residual"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--legs", default="main,ensemble,adjoint",

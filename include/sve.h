@@ -158,11 +158,21 @@ const char *sve_strerror(int code);
  *                    the wave speeds of step n+1 in a single pass;
  *   SVE_PATH_SPLIT   two kernels per step (update, then wave speeds);
  *   SVE_PATH_RESIDENT (1D only, nx <= 8192) one workgroup keeps the whole
- *                    grid in LDS and runs all n steps in one launch.
+ *                    grid in LDS and runs all n steps in one launch;
+ *   SVE_PATH_RESIDUAL (2D CFL steps; 1D and fixed-dt steps run as FUSED)
+ *                    one kernel per step that applies U - dt R of the
+ *                    previous pass and solves the new state's interfaces
+ *                    once, keeping the residual R (32 bytes per cell, FP64,
+ *                    two buffers allocated on first use) for the next step.
+ *                    An interface error of the state reached by a call's
+ *                    last step is then found one step early; it is reported
+ *                    by the next stepping call, as with the other paths.
+ * Results agree across paths to rounding.
  */
 #define SVE_PATH_FUSED    0
 #define SVE_PATH_SPLIT    1
 #define SVE_PATH_RESIDENT 2
+#define SVE_PATH_RESIDUAL 3
 int sve_set_path(sve_ctx *ctx, int path);
 
 /*

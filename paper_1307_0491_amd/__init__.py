@@ -9,7 +9,7 @@ from . import _lib
 from ._lib import (LAW_GRASS, LAW_MPM, LAW_FLVB, LAW_NIELSEN, LAW_RIBBERINK,
                    LAW_CAMENEN, FRIC_STRICKLER, FRIC_MANNING, FRIC_DARCY,
                    BC_PERIODIC, BC_FREE, BC_INFLOW, FP64, FP32, PATH_FUSED,
-                   PATH_SPLIT, PATH_RESIDENT, SveError)
+                   PATH_SPLIT, PATH_RESIDENT, PATH_RESIDUAL, SveError)
 from .solver import Params, BC, Solver, current_stream_handle
 
 
@@ -26,6 +26,6 @@ __all__ = [
     "LAW_GRASS", "LAW_MPM", "LAW_FLVB", "LAW_NIELSEN", "LAW_RIBBERINK",
     "LAW_CAMENEN", "FRIC_STRICKLER", "FRIC_MANNING", "FRIC_DARCY",
     "BC_PERIODIC", "BC_FREE", "BC_INFLOW", "FP64", "FP32", "PATH_FUSED",
-    "PATH_SPLIT", "PATH_RESIDENT", "SveError", "Params", "BC", "Solver",
+    "PATH_SPLIT", "PATH_RESIDENT", "PATH_RESIDUAL", "SveError", "Params", "BC", "Solver",
     "current_stream_handle", "require_device",
 ]

@@ -23,7 +23,7 @@ LAW_GRASS, LAW_MPM, LAW_FLVB, LAW_NIELSEN, LAW_RIBBERINK, LAW_CAMENEN = range(6)
 FRIC_STRICKLER, FRIC_MANNING, FRIC_DARCY = range(3)
 BC_PERIODIC, BC_FREE, BC_INFLOW = range(3)
 FP64, FP32 = 0, 1
-PATH_FUSED, PATH_SPLIT, PATH_RESIDENT = 0, 1, 2
+PATH_FUSED, PATH_SPLIT, PATH_RESIDENT, PATH_RESIDUAL = 0, 1, 2, 3
 
 
 class SveParams(ctypes.Structure):

@@ -13,6 +13,7 @@
 #include "sve_kernels.hpp"
 #include "sve_fused.hpp"
 #include "sve_resident.hpp"
+#include "sve_residual.hpp"
 
 using namespace sve;
 
@@ -172,10 +173,30 @@ void launch_fused(sve_ctx* c, int src, int dst, int n, double cfl, double t_end,
                          fused_tiles_y(c->M.nx, c->M.ny, c->fused_ty, c->wave_slots), c->stream);
 }
 
+StateView<double> rview(sve_ctx* c, int b) {
+    double* p = c->rbuf[b];
+    return StateView<double>{p, p + c->pitch, p + 2 * c->pitch, p + 3 * c->pitch};
+}
+
 template <typename T>
 int run_steps(sve_ctx* c, int n, double cfl, double t_end, double fixed_dt) {
     const bool cfl_mode = !(fixed_dt > 0.0);
-    if (cfl_mode && !c->speeds_valid) {
+    const bool resid = cfl_mode && c->path == SVE_PATH_RESIDUAL && c->M.dim == 2;
+    c->last_resid = resid;
+    const int tiles_y = fused_tiles_y(c->M.nx, c->M.ny, c->fused_ty, c->wave_slots);
+    if (resid) {
+        for (int b = 0; b < 2; ++b)
+            if (!c->rbuf[b])
+                HIP_TRY(hipMalloc((void**)&c->rbuf[b], 4 * (size_t)c->pitch * sizeof(double)));
+        if (!c->resid_valid) {
+            // residual and wave speeds of the current state
+            const int slot = (int)(c->nsteps % 3);
+            hipLaunchKernelGGL(k_clear_slot, dim3(1), dim3(64), 0, c->stream, c->ctrl, slot);
+            launch_resid<T, true>(c->M, view_of<T>(c, c->cur), rview(c, c->cur),
+                                  view_of<T>(c, c->cur), rview(c, c->cur), c->Ag, c->ctrl,
+                                  (int)c->nsteps, cfl, t_end, tiles_y, c->stream);
+        }
+    } else if (cfl_mode && !c->speeds_valid) {
         // wave speeds of the current state into the slot of the next step
         const int slot = (int)(c->nsteps % 3);
         hipLaunchKernelGGL(k_clear_slot, dim3(1), dim3(64), 0, c->stream, c->ctrl, slot);
@@ -188,7 +209,12 @@ int run_steps(sve_ctx* c, int n, double cfl, double t_end, double fixed_dt) {
         for (int s = 0; s < n; ++s) {
             const int step = (int)(c->nsteps + s);
             const int src = (c->cur + s) & 1, dst = src ^ 1;
-            if (c->path == SVE_PATH_FUSED && c->M.dim == 2) {
+            if (resid) {
+                launch_resid<T, false>(c->M, view_of<T>(c, src), rview(c, src), view_of<T>(c, dst),
+                                       rview(c, dst), c->Ag, c->ctrl, step, cfl, t_end, tiles_y,
+                                       c->stream);
+            } else if ((c->path == SVE_PATH_FUSED || c->path == SVE_PATH_RESIDUAL) &&
+                       c->M.dim == 2) {
                 launch_fused<T>(c, src, dst, step, cfl, t_end, fixed_dt);
             } else {
                 launch_update<T>(c, src, dst, step, cfl, t_end, fixed_dt);
@@ -199,6 +225,7 @@ int run_steps(sve_ctx* c, int n, double cfl, double t_end, double fixed_dt) {
     (void)hipEventRecord(c->ev1, c->stream);
     HIP_TRY(hipGetLastError());
     c->speeds_valid = cfl_mode;
+    c->resid_valid = resid;
     return SVE_OK;
 }
 
@@ -208,6 +235,19 @@ int finish_steps(sve_ctx* c, int n) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) c->last_ms = ms;
     const Ctrl& h = *c->h_ctrl;
+    if (h.err && c->last_resid && h.fail_step == c->nsteps + n) {
+        // the residual pass found an interface error of the state its last
+        // step reached: the n steps completed; the next step fails
+        c->cur = (int)((c->cur + n) & 1);
+        c->nsteps += n;
+        c->t = h.t[c->nsteps % 3];
+        c->dt_last = h.dt_last;
+        c->pending = code_from_bits(h.err);
+        if (c->pending == SVE_OK) c->pending = SVE_ERR_STATE;
+        c->speeds_valid = false;
+        c->resid_valid = false;
+        return SVE_OK;
+    }
     if (h.err) {
         long long fail = h.fail_step;
         if (fail < c->nsteps || fail >= c->nsteps + n) fail = c->nsteps;
@@ -218,6 +258,7 @@ int finish_steps(sve_ctx* c, int n) {
         c->sticky = code_from_bits(h.err);
         if (c->sticky == SVE_OK) c->sticky = SVE_ERR_STATE;
         c->speeds_valid = false;
+        c->resid_valid = false;
         return c->sticky;
     }
     c->cur = (int)((c->cur + n) & 1);
@@ -231,6 +272,11 @@ int do_steps(sve_ctx* c, int n, double cfl, double t_end, double fixed_dt) {
     if (!c) return SVE_ERR_ARG;
     if (c->sticky) return c->sticky;
     if (n < 0) return SVE_ERR_ARG;
+    if (c->pending && n > 0) {                   // the first of these steps fails
+        c->sticky = c->pending;
+        c->pending = SVE_OK;
+        return c->sticky;
+    }
     if (n == 0) return SVE_OK;
     if (c->nsteps + n >= INT_MAX) return SVE_ERR_ARG;
     int rc = c->storage == SVE_FP32 ? run_steps<float>(c, n, cfl, t_end, fixed_dt)
@@ -431,6 +477,8 @@ int sve_destroy(sve_ctx* ctx) {
     if (ctx->h_ctrl) (void)hipHostFree(ctx->h_ctrl);
     if (ctx->Ag) (void)hipFree(ctx->Ag);
     if (ctx->staging) (void)hipFree(ctx->staging);
+    for (int b = 0; b < 2; ++b)
+        if (ctx->rbuf[b]) (void)hipFree(ctx->rbuf[b]);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     sve_adjoint_release(ctx);
@@ -453,7 +501,8 @@ const char* sve_strerror(int code) {
 
 int sve_set_path(sve_ctx* ctx, int path) {
     if (!ctx) return SVE_ERR_ARG;
-    if (path != SVE_PATH_FUSED && path != SVE_PATH_SPLIT && path != SVE_PATH_RESIDENT)
+    if (path != SVE_PATH_FUSED && path != SVE_PATH_SPLIT && path != SVE_PATH_RESIDENT &&
+        path != SVE_PATH_RESIDUAL)
         return SVE_ERR_ARG;
     if (path == SVE_PATH_RESIDENT && !resident_supported(ctx)) return SVE_ERR_ARG;
     ctx->path = path;
@@ -476,6 +525,7 @@ int sve_debug_poke(sve_ctx* ctx, int field, long long k, double value) {
         hipLaunchKernelGGL(k_poke<double>, dim3(1), dim3(64), 0, ctx->stream,
                            view_of<double>(ctx, ctx->cur), field, k, value);
     ctx->speeds_valid = false;
+    ctx->resid_valid = false;
     return check_hip(hipStreamSynchronize(ctx->stream));
 }
 

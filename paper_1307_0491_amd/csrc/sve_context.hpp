@@ -29,6 +29,10 @@ struct sve_ctx {
     int wave_slots = 2048;      // resident wavefronts of the step kernels on the device
     int sticky = SVE_OK;
     bool speeds_valid = false;  // slot nsteps%3 holds the speeds of the state
+    double* rbuf[2] = {nullptr, nullptr};  // residuals of the residual path (FP64, 4 fields)
+    bool resid_valid = false;   // rbuf[cur] and slot nsteps%3 belong to the state
+    bool last_resid = false;    // the last run_steps used the residual path
+    int pending = SVE_OK;       // error of the step after the last call (residual path)
     double last_ms = 0.0;
     sve_adjoint_state* adj = nullptr;
 };

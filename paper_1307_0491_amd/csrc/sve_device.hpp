@@ -324,8 +324,9 @@ __device__ __forceinline__ double iface_speed(const Side& L, const Side& R, doub
 }
 
 // Fluxes of the exact relaxation Riemann solution; returns ERR_* bits.
+// `speed` receives the largest outer wave speed max(|sigma1|, |sigma5|).
 __device__ __forceinline__ unsigned iface_flux(const Side& L, const Side& R, double g,
-                                               Flux& F) {
+                                               Flux& F, double& speed) {
     const Celer C = celerities(L, R, g);
     const double a = C.a, b = C.b, c = C.c, a2 = C.a2, kappa = C.kappa, dZ = C.dZ;
     const double PL = L.Pi + a2 * L.tau;
@@ -380,7 +381,14 @@ __device__ __forceinline__ unsigned iface_flux(const Side& L, const Side& R, dou
     F.FhuR = P0 + C.gHbar * (Z0 - R.z);
     F.Fht = F.Fh * vt0;
     F.Fz = O0;
+    speed = fmax(fabs(AL), fabs(AR));
     return err;
+}
+
+__device__ __forceinline__ unsigned iface_flux(const Side& L, const Side& R, double g,
+                                               Flux& F) {
+    double speed;
+    return iface_flux(L, R, g, F, speed);
 }
 
 // Coefficient phi of the optional semi-implicit momentum friction,

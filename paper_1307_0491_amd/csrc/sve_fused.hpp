@@ -111,9 +111,50 @@ __device__ __forceinline__ void row_index(const Model& M, int r, int& jj, int& g
     gin = (g >= 0 && M.bc_kind[g] == BC_INFLOW) ? g : -1;
 }
 
+// Inflow values of the ghost cells a tile can touch and the uniform A_g,
+// read once per tile with constant indices.  (Indexing the model's arrays
+// with a lane- or row-dependent side inside the row loop reads them from
+// memory on every row, and those reads stall the loop's other loads.)
+struct Ghosts {
+    double xh, xhu, xhv;     // this lane's column ghost (used when gxin >= 0)
+    double sh, shu, shv;     // south ghost row
+    double nh, nhu, nhv;     // north ghost row
+    double ag;               // A_g when there is no per-cell field
+};
+
+__device__ __forceinline__ Ghosts make_ghosts(const Model& M, int gxin) {
+    Ghosts g;
+    const bool w = gxin == BCW;
+    g.xh = w ? M.bc_h[BCW] : M.bc_h[BCE];
+    g.xhu = w ? M.bc_hu[BCW] : M.bc_hu[BCE];
+    g.xhv = w ? M.bc_hv[BCW] : M.bc_hv[BCE];
+    g.sh = M.bc_h[BCS];
+    g.shu = M.bc_hu[BCS];
+    g.shv = M.bc_hv[BCS];
+    g.nh = M.bc_h[BCN];
+    g.nhu = M.bc_hu[BCN];
+    g.nhv = M.bc_hv[BCN];
+    g.ag = M.Ag;
+    return g;
+}
+
+// (h, hu, hv) of an INFLOW ghost: x ghost of this lane (gxin >= 0), then
+// the ghost row (gyin = BCS or BCN).
+__device__ __forceinline__ void apply_inflow(const Ghosts& G, int gxin, int gyin, double& h,
+                                             double& hu, double& hv) {
+    if (gxin >= 0) { h = G.xh; hu = G.xhu; hv = G.xhv; }
+    if (gyin >= 0) {
+        const bool s = gyin == BCS;
+        h = s ? G.sh : G.nh;
+        hu = s ? G.shu : G.nhu;
+        hv = s ? G.shv : G.nhv;
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ Raw load_row(const Model& M, const StateView<T>& S,
-                                        const double* __restrict__ Agf, int ci, int gxin, int r) {
+                                        const double* __restrict__ Agf, const Ghosts& G, int ci,
+                                        int gxin, int r) {
     int jj, gyin;
     row_index(M, r, jj, gyin);
     const long long k = (long long)jj * M.nx + ci;
@@ -122,9 +163,8 @@ __device__ __forceinline__ Raw load_row(const Model& M, const StateView<T>& S,
     w.hu = (double)S.hu[k];
     w.hv = (double)S.hv[k];
     w.z = (double)S.z[k];
-    w.ag = Agf ? Agf[k] : M.Ag;
-    if (gxin >= 0) { w.h = M.bc_h[gxin]; w.hu = M.bc_hu[gxin]; w.hv = M.bc_hv[gxin]; }
-    if (gyin >= 0) { w.h = M.bc_h[gyin]; w.hu = M.bc_hu[gyin]; w.hv = M.bc_hv[gyin]; }
+    w.ag = Agf ? Agf[k] : G.ag;
+    apply_inflow(G, gxin, gyin, w.h, w.hu, w.hv);
     return w;
 }
 
@@ -143,6 +183,12 @@ struct RowCarry {
     unsigned eX, eY;
     double Yh, Yt, YR, Yz;                                     // y-flux below row r-1
     Side N;                                                    // y view, new state of row r-2
+    // new state of the row updated last, stored at the start of the next
+    // row: a store issued just before the loop's wait for the next row's
+    // loads would hold the wavefront until the write completes
+    double ph, phu, phv, pz;
+    long long pk;
+    bool pend;
 };
 
 // One tile of one step, run by one wavefront: tile tx owns columns
@@ -174,14 +220,20 @@ __device__ __forceinline__ void fused_tile(const Model& M, const StateView<T>& S
         if (M.bc_kind[BCE] == BC_PERIODIC) ci = wrap(col, M.nx); else { ci = M.nx - 1; gx = BCE; }
     }
     const int gxin = (gx >= 0 && M.bc_kind[gx] == BC_INFLOW) ? gx : -1;
+    const Ghosts G = make_ghosts(M, gxin);
     double sx = 0.0, sy = 0.0;
 
     // Row r with the row loaded for it in `cur`.  DO_X: x-interfaces of row
     // r; DO_UPD: update of row r-1 (RING: that row is the ring row, not
     // stored); FIRST_UPD: row r-1 is the first owned row (no y-speed below
     // it yet, south boundary speed instead).
+    auto flush = [&](RowCarry& c) {
+        if (c.pend) store_cell(M, D, c.pk, c.ph, c.phu, c.phv, c.pz);
+        c.pend = false;
+    };
     auto row = [&](RowCarry& c, const Raw& cur, int r, auto do_x, auto do_upd, auto ring,
                    auto first_upd) {
+        flush(c);
         const Cell P = project<CL>(M, cur.h, cur.hu, cur.hv, cur.z, cur.ag);
         double dXh = 0, dXm = 0, dXt = 0, dXz = 0;
         unsigned eXn = 0;
@@ -207,7 +259,12 @@ __device__ __forceinline__ void fused_tile(const Model& M, const StateView<T>& S
             if (!ring.value && owned_lane) {
                 const unsigned e = check_state(hn, hun, hvn, zn) | c.eX | c.eY | eY;
                 if (e) record_error(ctrl, e, n);
-                store_cell(M, D, (long long)ru * M.nx + col, hn, hun, hvn, zn);
+                c.pend = true;
+                c.pk = (long long)ru * M.nx + col;
+                c.ph = hn;
+                c.phu = hun;
+                c.phv = hvn;
+                c.pz = zn;
             }
             if (SPEEDS) {
                 if (xghost_e) {                      // ring lane is the east ghost
@@ -260,31 +317,32 @@ __device__ __forceinline__ void fused_tile(const Model& M, const StateView<T>& S
     // row j0-1: projection only
     RowCarry c{};
     {
-        const Raw w = load_row(M, S, Agf, ci, gxin, j0 - 1);
+        const Raw w = load_row(M, S, Agf, G, ci, gxin, j0 - 1);
         const Cell P = project<CL>(M, w.h, w.hu, w.hv, w.z, w.ag);
         c.h = P.h; c.tau = P.tau; c.u = P.u; c.v = P.v; c.Pi = P.Pi; c.z = P.z; c.qy = P.qy;
         c.by2 = P.by2; c.aK = P.aK; c.inv = P.inv_aK; c.hu = P.hu; c.hv = P.hv; c.ag = w.ag;
     }
-    Raw cur = load_row(M, S, Agf, ci, gxin, j0);
-    Raw nxt = load_row(M, S, Agf, ci, gxin, j0 + 1);
+    Raw cur = load_row(M, S, Agf, G, ci, gxin, j0);
+    Raw nxt = load_row(M, S, Agf, G, ci, gxin, j0 + 1);
     row(c, cur, j0, Y_{}, N_{}, N_{}, N_{});                       // row j0: fluxes only
     cur = nxt;
     if (j0 + 1 < j_ring) {
-        nxt = load_row(M, S, Agf, ci, gxin, j0 + 2);
+        nxt = load_row(M, S, Agf, G, ci, gxin, j0 + 2);
         row(c, cur, j0 + 1, Y_{}, Y_{}, N_{}, Y_{});               // update of row j0
         cur = nxt;
         for (int r = j0 + 2; r < j_ring; ++r) {                   // owned rows j0+1 .. jend-2
-            nxt = load_row(M, S, Agf, ci, gxin, r + 1);
+            nxt = load_row(M, S, Agf, G, ci, gxin, r + 1);
             row(c, cur, r, Y_{}, Y_{}, N_{}, N_{});
             cur = nxt;
         }
-        nxt = load_row(M, S, Agf, ci, gxin, j_ring + 1);
+        nxt = load_row(M, S, Agf, G, ci, gxin, j_ring + 1);
         row(c, cur, j_ring, Y_{}, Y_{}, N_{}, N_{});               // update of row jend-1
     } else {                                                       // one owned row
-        nxt = load_row(M, S, Agf, ci, gxin, j_ring + 1);
+        nxt = load_row(M, S, Agf, G, ci, gxin, j_ring + 1);
         row(c, cur, j_ring, Y_{}, Y_{}, N_{}, Y_{});
     }
     row(c, nxt, j_ring + 1, N_{}, Y_{}, Y_{}, N_{});               // ring row (speeds only)
+    flush(c);
     if (SPEEDS) {
         sx = wave_max(sx);
         sy = wave_max(sy);

@@ -69,10 +69,13 @@ def per(sve):
     return [sve.BC(sve.BC_PERIODIC)] * 4
 
 
-@pytest.mark.parametrize("path", ["fused", "split"])
+PATHS = {"fused": 0, "split": 1, "residual": 3}
+
+
+@pytest.mark.parametrize("path", ["fused", "split", "residual"])
 def test_dune2d_periodic_fp64(sve, path):
     case = dune2d_case(150, 80)
-    p = sve.PATH_FUSED if path == "fused" else sve.PATH_SPLIT
+    p = PATHS[path]
     f, t, dtl, ns, o = run_pair(sve, case, grass(sve), per(sve), 60, path=p)
     assert ns == 60
     assert t == pytest.approx(o.t, rel=TOL64)
@@ -82,41 +85,45 @@ def test_dune2d_periodic_fp64(sve, path):
 
 # rows: one-row tiles, uneven splits (75 rows in tiles of 5 and 8 rows, or
 # of 16 with a short last tile), one tile taller than the grid, automatic
+@pytest.mark.parametrize("path", ["fused", "residual"])
 @pytest.mark.parametrize("rows", [1, 5, 8, 16, 64, 100, 0])
-def test_fused_tile_rows_agree(sve, rows):
+def test_fused_tile_rows_agree(sve, rows, path):
     case = dune2d_case(130, 75)
-    f, t, dtl, ns, o = run_pair(sve, case, grass(sve, Ag=0.05), per(sve), 30, rows=rows)
+    f, t, dtl, ns, o = run_pair(sve, case, grass(sve, Ag=0.05), per(sve), 30, rows=rows,
+                                path=PATHS[path])
     assert t == pytest.approx(o.t, rel=TOL64)
     assert_fields_close(f, o.state, TOL64)
 
 
+@pytest.mark.parametrize("path", ["fused", "residual"])
 @pytest.mark.parametrize("rows", [1, 3, 0])
-def test_fused_tile_rows_open_boundaries(sve, rows):
+def test_fused_tile_rows_open_boundaries(sve, rows, path):
     """Tiles touching inflow and free boundaries, with uneven splits."""
     case = mpm_case(160, 70)
     bcs = [sve.BC(sve.BC_INFLOW, 0.5, 2.0, 0.0), sve.BC(sve.BC_FREE),
            sve.BC(sve.BC_FREE), sve.BC(sve.BC_FREE)]
-    f, t, dtl, ns, o = run_pair(sve, case, mpm(sve), bcs, 40, rows=rows)
+    f, t, dtl, ns, o = run_pair(sve, case, mpm(sve), bcs, 40, rows=rows, path=PATHS[path])
     assert t == pytest.approx(o.t, rel=TOL64)
     assert_fields_close(f, o.state, TOL64)
 
 
-@pytest.mark.parametrize("path", ["fused", "split"])
+@pytest.mark.parametrize("path", ["fused", "split", "residual"])
 def test_mpm_strickler_inflow_free_fp64(sve, path):
     case = mpm_case(160, 70)
     bcs = [sve.BC(sve.BC_INFLOW, 0.5, 2.0, 0.0), sve.BC(sve.BC_FREE),
            sve.BC(sve.BC_FREE), sve.BC(sve.BC_FREE)]
-    p = sve.PATH_FUSED if path == "fused" else sve.PATH_SPLIT
+    p = PATHS[path]
     f, t, dtl, ns, o = run_pair(sve, case, mpm(sve), bcs, 80, path=p)
     assert t == pytest.approx(o.t, rel=TOL64)
     assert_fields_close(f, o.state, TOL64)
 
 
-def test_mpm_fp32_storage(sve):
+@pytest.mark.parametrize("path", ["fused", "residual"])
+def test_mpm_fp32_storage(sve, path):
     case = mpm_case(160, 70)
     bcs = [sve.BC(sve.BC_INFLOW, 0.5, 2.0, 0.0), sve.BC(sve.BC_FREE),
            sve.BC(sve.BC_FREE), sve.BC(sve.BC_FREE)]
-    f, t, dtl, ns, o = run_pair(sve, case, mpm(sve), bcs, 80, storage="fp32")
+    f, t, dtl, ns, o = run_pair(sve, case, mpm(sve), bcs, 80, storage="fp32", path=PATHS[path])
     assert t == pytest.approx(o.t, rel=TOL32)
     assert_fields_close(f, o.state, TOL32)
     for a in f:
@@ -124,33 +131,66 @@ def test_mpm_fp32_storage(sve):
 
 
 @pytest.mark.parametrize("mg", [1.0, 1.7, 2.5, 4.0])
-def test_grass_exponent_and_ag_field(sve, mg):
+@pytest.mark.parametrize("path", ["fused", "residual"])
+def test_grass_exponent_and_ag_field(sve, mg, path):
     case = dune2d_case(100, 66)
     rng = np.random.default_rng(5)
     Ag = 1e-2 * (1.0 + 0.3 * rng.uniform(-1, 1, case["h"].shape))
     case["hv"] = 0.5 * case["zb"]
-    f, t, dtl, ns, o = run_pair(sve, case, grass(sve, Ag=1e-2, mg=mg), per(sve), 40, Ag=Ag)
+    f, t, dtl, ns, o = run_pair(sve, case, grass(sve, Ag=1e-2, mg=mg), per(sve), 40, Ag=Ag,
+                                path=PATHS[path])
     assert t == pytest.approx(o.t, rel=TOL64)
     assert_fields_close(f, o.state, TOL64)
 
 
 @pytest.mark.parametrize("law", ["FLVB", "NIELSEN", "RIBBERINK", "CAMENEN"])
 @pytest.mark.parametrize("fric", ["MANNING", "DARCY"])
-def test_other_bedload_laws(sve, law, fric):
+@pytest.mark.parametrize("path", ["fused", "residual"])
+def test_other_bedload_laws(sve, law, fric, path):
     case = mpm_case(90, 40)
     case["hv"] = 0.2 * np.sin(np.arange(case["h"].size).reshape(case["h"].shape) * 0.01)
     coef = 0.025 if fric == "MANNING" else 0.05
     p = mpm(sve, law=getattr(sve, "LAW_" + law), friction=getattr(sve, "FRIC_" + fric),
             coef=coef)
-    f, t, dtl, ns, o = run_pair(sve, case, p, per(sve), 25)
+    f, t, dtl, ns, o = run_pair(sve, case, p, per(sve), 25, path=PATHS[path])
     assert_fields_close(f, o.state, TOL64)
 
 
-def test_momentum_friction(sve):
+@pytest.mark.parametrize("path", ["fused", "residual"])
+def test_momentum_friction(sve, path):
     case = mpm_case(120, 40)
     bcs = [sve.BC(sve.BC_INFLOW, 0.5, 2.0, 0.0), sve.BC(sve.BC_FREE),
            sve.BC(sve.BC_PERIODIC), sve.BC(sve.BC_PERIODIC)]
-    f, t, dtl, ns, o = run_pair(sve, case, mpm(sve, momentum_friction=1), bcs, 40)
+    f, t, dtl, ns, o = run_pair(sve, case, mpm(sve, momentum_friction=1), bcs, 40,
+                                path=PATHS[path])
+    assert_fields_close(f, o.state, TOL64)
+
+
+def test_paths_and_fixed_dt_mixed_in_one_run(sve):
+    """Residual, fixed-dt, fused and split steps in one run: the residual
+    path rebuilds its residual after any other kind of step."""
+    case = dune2d_case(120, 70)
+    case["hv"] = 0.3 * case["zb"]
+    p = grass(sve, Ag=0.03, mg=2.5)
+    s = sve.Solver(case["h"], case["hu"], case["zb"], case["hv"], lx=case["lx"],
+                   ly=case["ly"], params=p, bcs=per(sve))
+    ny, nx = case["h"].shape
+    o = O.Oracle2D(case["h"], case["hu"], case["hv"], case["zb"], case["lx"] / nx,
+                   case["ly"] / ny, to_oracle_params(p), to_oracle_bcs(per(sve)))
+    plan = [("residual", 7), ("fixed", 4), ("residual", 6), ("fused", 3), ("residual", 1),
+            ("split", 2), ("residual", 5)]
+    for kind, n in plan:
+        if kind == "fixed":
+            s.step_fixed_dt(n, 0.004)
+            o.step_fixed_dt(n, 0.004)
+        else:
+            s.set_path(PATHS[kind])
+            s.step(n, 0.5)
+            o.step(n, 0.5)
+    f, t, dtl, ns = s.get_state()
+    s.close()
+    assert ns == sum(n for _, n in plan)
+    assert t == pytest.approx(o.t, rel=TOL64)
     assert_fields_close(f, o.state, TOL64)
 
 
@@ -169,7 +209,7 @@ def test_tiny_and_degenerate_2d_grids(sve, shape):
     case = dict(h=h, hu=0.5 + 0.2 * rng.uniform(size=shape), hv=0.1 * rng.uniform(size=shape),
                 zb=0.1 * rng.uniform(size=shape), lx=10.0 * nx, ly=10.0 * ny)
     for bcs in (per(sve), [sve.BC(sve.BC_FREE)] * 4):
-        for path in (sve.PATH_FUSED, sve.PATH_SPLIT):
+        for path in (sve.PATH_FUSED, sve.PATH_SPLIT, sve.PATH_RESIDUAL):
             f, t, dtl, ns, o = run_pair(sve, case, grass(sve, Ag=0.01), bcs, 15, path=path)
             assert_fields_close(f, o.state, TOL64)
 
