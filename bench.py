@@ -122,6 +122,70 @@ def copy_calibration(torch, mib: int, reps: int = 5):
     return {"bytes_read": 8 * n, "bytes_written": 8 * n, "reps": reps}
 
 
+def mpm_leg(args, sve, torch):
+    """Meyer-Peter & Mueller channel, Strickler K_s = 40, 8192 x 2048 cells on
+    4000 x 1000 m, inflow (h 0.5, hu 2) and free boundaries; FP64 storage
+    and FP32 storage (FP64 arithmetic)."""
+    import workloads as W
+    h, hu, hv, zb, dx, dy = W.mpm_channel()
+    ny, nx = h.shape
+    p = sve.Params(law=sve.LAW_MPM, friction=sve.FRIC_STRICKLER, fric_coef=40.0, d_s=1e-3,
+                   s=2.65, tau_cr=0.05)
+    bcs = [sve.BC(sve.BC_INFLOW, 0.5, 2.0, 0.0), sve.BC(sve.BC_FREE), sve.BC(sve.BC_FREE),
+           sve.BC(sve.BC_FREE)]
+    out = {"nx": nx, "ny": ny, "steps": args.mpm_steps, "warmup": args.mpm_warmup}
+    for storage, bpc in (("fp64", 64.0), ("fp32", 32.0)):
+        s = sve.Solver(h, hu, zb, hv, lx=4000.0, ly=1000.0, params=p, bcs=bcs, storage=storage,
+                       stream=sve.current_stream_handle())
+        s.step(args.mpm_warmup, 0.5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(args.mpm_steps, 0.5)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        per_launch = s.last_elapsed_ms() * 1e-3 / args.mpm_steps
+        (gh, _, _, _), t, _, _ = s.get_state()
+        s.close()
+        achieved = bpc * nx * ny / per_launch / 1e9
+        out[storage] = {"cell_updates_per_s": nx * ny * args.mpm_steps / wall,
+                        "ms_per_step": wall * 1e3 / args.mpm_steps,
+                        "avg_launch_us": per_launch * 1e6, "bytes_per_cell": bpc,
+                        "hbm_achieved_GBs": achieved, "hbm_frac": achieved / HBM_PEAK_GBS,
+                        "sim_time_s": t, "finite": bool(np.all(np.isfinite(gh)))}
+        progress(f"mpm {storage}: {args.mpm_steps} steps in {wall:.3f} s")
+    return out
+
+
+# CFL-0.5 steps of the 1D dune from t = 0 to T = 10000 s, the last one
+# clipped to land on T (the oracle's count; the full-size parity test checks
+# that the library takes the same steps).
+DUNE1D_STEPS = 218402
+
+
+def dune1d_leg(args, sve, torch):
+    """1D Grass dune, 1000 cells on [0, 1000] m, periodic, CFL 0.5, run to
+    T = 10000 s (default path: one workgroup with the grid in LDS)."""
+    import workloads as W
+    h, hu, zb, dx = W.dune1d(1000)
+    p = sve.Params(law=sve.LAW_GRASS, A_g=1e-3, m_g=3.0)
+    s = sve.Solver(h, hu, zb, lx=1000.0, params=p, bcs=[sve.BC(sve.BC_PERIODIC)] * 2,
+                   stream=sve.current_stream_handle())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t = s.step(DUNE1D_STEPS, 0.5, 10000.0)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    (gh, _, _), _, dtl, _ = s.get_state()
+    s.close()
+    progress(f"dune1d: T = {t} s in {wall:.3f} s")
+    out = {"nx": 1000, "t_end": t, "steps": DUNE1D_STEPS, "wall_s": wall,
+           "cell_updates_per_s": 1000.0 * DUNE1D_STEPS / wall,
+           "us_per_step": wall * 1e6 / DUNE1D_STEPS, "last_dt": dtl}
+    if t != 10000.0 or not dtl > 0.0:
+        out["error"] = "the run did not end on T with its last step"
+    return out
+
+
 def ensemble_leg(args, sve, torch):
     import workloads as W
     from paper_1307_0491_amd.ensemble import Ensemble
@@ -248,8 +312,10 @@ def main():
     ap.add_argument("--path", default="fused", choices=["fused", "split", "residual"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=3)
-    ap.add_argument("--legs", default="main,ensemble,adjoint",
-                    help="comma list of main, ensemble, adjoint")
+    ap.add_argument("--legs", default="main,mpm,dune1d,ensemble,adjoint",
+                    help="comma list of main, mpm, dune1d, ensemble, adjoint")
+    ap.add_argument("--mpm-steps", type=int, default=200)
+    ap.add_argument("--mpm-warmup", type=int, default=10)
     ap.add_argument("--ens-members", type=int, default=256)
     ap.add_argument("--ens-steps", type=int, default=1000)
     ap.add_argument("--ens-seq-steps", type=int, default=100)
@@ -304,6 +370,10 @@ def main():
             out["error"] = "non-finite or non-positive depth after the run"
     if args.copy_calib:
         out["copy_calibration"] = copy_calibration(torch, args.copy_calib)
+    if "mpm" in legs:
+        out["mpm"] = mpm_leg(args, sve, torch)
+    if "dune1d" in legs:
+        out["dune1d"] = dune1d_leg(args, sve, torch)
     if "ensemble" in legs:
         out["ensemble"] = ensemble_leg(args, sve, torch)
     if "adjoint" in legs:

@@ -153,8 +153,10 @@ int sve_destroy(sve_ctx *ctx);
 const char *sve_strerror(int code);
 
 /*
- * Path selection for tests and measurements (not needed in normal use):
- *   SVE_PATH_FUSED   (default) one kernel per step: update of step n and
+ * Path selection for tests and measurements (not needed in normal use).
+ * The default is SVE_PATH_RESIDENT for 1D grids it supports, else
+ * SVE_PATH_FUSED.
+ *   SVE_PATH_FUSED   one kernel per step: update of step n and
  *                    the wave speeds of step n+1 in a single pass;
  *   SVE_PATH_SPLIT   two kernels per step (update, then wave speeds);
  *   SVE_PATH_RESIDENT (1D only, nx <= 8192) one workgroup keeps the whole

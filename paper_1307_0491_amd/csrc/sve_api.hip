@@ -301,6 +301,8 @@ int init_common(sve_ctx* c, const double* h, const double* hu, const double* hv,
     launch_speeds<T>(c, 0, 0);
     HIP_TRY(hipGetLastError());
     c->speeds_valid = true;
+    // 1D grids that fit in one workgroup's LDS run on the resident kernel
+    if (resident_supported(c)) c->path = SVE_PATH_RESIDENT;
     return SVE_OK;
 }
 
