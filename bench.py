@@ -46,8 +46,8 @@ NX = NY = 2000
 # WRITE_SIZE x 1.0000.  Valid only for the kernel sources it was taken on
 # (hash of the HIP sources) and the automatic tile split; otherwise the bench
 # reports null.  Summary: profiles/k_fused_dune2000_fp64_hbm_traffic.md.
-TRAFFIC = {"src": "978d9950cca58c61", "rows": 0,
-           "fetch_kib": 88282.9, "write_kib": 131127.9,
+TRAFFIC = {"src": "c25a809a115bf184", "rows": 0,
+           "fetch_kib": 88282.5, "write_kib": 131127.9,
            "bytes_per_launch": 315.07e6}
 
 
