@@ -6,10 +6,10 @@
 //              patterns).
 //   k_update   one thread per cell: five-point stencil, four interface
 //              solves, conservative update (split path and reference).
-//   k_fused    one workgroup per tile, LDS-staged: the update of step n for
-//              the tile plus the wave speeds of step n+1 on the interfaces
-//              the tile owns, using a one-cell redundant ring of new states
-//              so that no second pass over the grid is needed.
+// plus the per-cell helpers the row kernels share (error bits, stores,
+// friction, step bookkeeping).  The one-pass 2D kernels are in
+// sve_fused.hpp (k_fused) and sve_residual.hpp (k_resid), the 1D
+// LDS-resident kernel in sve_resident.hpp.
 #pragma once
 
 #include "sve_device.hpp"
