@@ -43,21 +43,21 @@ NX = NY = 2000
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each
 # scaled by the ratio of known bytes to the same counter on a plain
 # streaming kernel (1 GiB read, 1 GiB written): FETCH_SIZE x 2.0000,
-# WRITE_SIZE x 1.0000.  Valid only for the kernel sources it was taken on
-# (hash of the HIP sources) and the automatic tile split; otherwise the bench
-# reports null.  Summary: profiles/k_fused_dune2000_fp64_hbm_traffic.md.
-TRAFFIC = {"src": "c25a809a115bf184", "rows": 0,
+# WRITE_SIZE x 1.0000.  Valid only for the library build it was taken on
+# (hash of the built library) and the automatic tile split; otherwise the
+# bench reports null.  Summary: profiles/k_fused_dune2000_fp64_hbm_traffic.md.
+TRAFFIC = {"src": "7348180f4420a1c2", "rows": 0,
            "fetch_kib": 88282.5, "write_kib": 131127.9,
            "bytes_per_launch": 315.07e6}
 
 
 def kernel_source_hash() -> str:
-    d = os.path.join(ROOT, "paper_1307_0491_amd", "csrc")
+    """Hash of the built HIP library (its code objects hold the kernels;
+    rebuilding unchanged sources gives the same file)."""
+    import paper_1307_0491_amd._lib as L
     h = hashlib.sha256()
-    for name in sorted(os.listdir(d)):
-        if name.endswith((".hpp", ".hip")):
-            with open(os.path.join(d, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    with open(L.LIB_PATH, "rb") as f:
+        h.update(f.read())
     return h.hexdigest()[:16]
 
 
