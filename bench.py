@@ -80,7 +80,21 @@ def cpu_baseline(nsteps: int = 3):
     return {"value": NX * NY * nsteps / el, "unit": "cell-updates/s", "cores": 1,
             "kind": "oracle",
             "sample": f"{nsteps} CFL steps of the full {NX}x{NY} grid, numpy FP64, one process",
-            "seconds": el}
+            "seconds": el, "host": host_cpu()}
+
+
+def host_cpu():
+    """CPU model and logical CPU count of the host the oracle ran on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "cpu_count": os.cpu_count()}
 
 
 def progress(msg):
@@ -183,6 +197,59 @@ def dune1d_leg(args, sve, torch):
            "us_per_step": wall * 1e6 / DUNE1D_STEPS, "last_dt": dtl}
     if t != 10000.0 or not dtl > 0.0:
         out["error"] = "the run did not end on T with its last step"
+    return out
+
+
+def run_to(s, t_end, cfl=0.5, chunk=1000):
+    """Advance solver s to t_end; returns the number of steps that advanced
+    the time (chunks of `chunk` steps while they stay clear of t_end, then
+    single steps, the last one clipped to land on t_end)."""
+    t = s.step(1, cfl, t_end)
+    steps = 1
+    dt = t
+    while t < t_end:
+        if t + 1.2 * chunk * dt < t_end:
+            t_new = s.step(chunk, cfl)
+            dt = (t_new - t) / chunk
+            steps += chunk
+        else:
+            t_new = s.step(1, cfl, t_end)
+            steps += 1
+        t = t_new
+    return steps
+
+
+def paper2d_leg(args, sve, torch):
+    """The paper's 2D bump cases (subsection "2D dune evolution cases"):
+    4000 x 4000 cells on [0, 1000]^2 m, z_b = 0.1 + bump, h = 10 - z_b,
+    hu = q0 = 10, hv = 0; inflow at x = 0 with (h, hu, hv) = (9.9, 10, 0), the
+    initial state there; free flow on the other sides; Grass m_g = 3 with
+    A_g = 1 to T = 500 s and A_g = 0.1 to T = 1000 s; CFL 0.5; FP64."""
+    import workloads as W
+    n = args.paper_n
+    h, hu, hv, zb, dx, dy = W.dune2d(n, n, base=0.1)
+    bcs = [sve.BC(sve.BC_INFLOW, 9.9, 10.0, 0.0), sve.BC(sve.BC_FREE), sve.BC(sve.BC_FREE),
+           sve.BC(sve.BC_FREE)]
+    out = {"nx": n, "ny": n}
+    for ag, t_end in ((1.0, 500.0), (0.1, 1000.0)):
+        s = sve.Solver(h, hu, zb, hv, lx=1000.0, ly=1000.0,
+                       params=sve.Params(law=sve.LAW_GRASS, A_g=ag, m_g=3.0), bcs=bcs,
+                       stream=sve.current_stream_handle())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps = run_to(s, t_end)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        (gh, _, _, gz), t, _, _ = s.get_state()
+        s.close()
+        k = int(np.argmax(gz))
+        out[f"A_g={ag:g}"] = {
+            "t_end": t, "steps": steps, "wall_s": wall,
+            "cell_updates_per_s": n * n * steps / wall,
+            "zb_max": float(gz.max()), "zb_max_at_m": [float((k % n + 0.5) * dx),
+                                                      float((k // n + 0.5) * dy)],
+            "finite": bool(np.all(np.isfinite(gh)) and np.all(gh > 0))}
+        progress(f"paper2d A_g={ag:g}: T = {t} s, {steps} steps in {wall:.1f} s")
     return out
 
 
@@ -313,7 +380,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--legs", default="main,mpm,dune1d,ensemble,adjoint",
-                    help="comma list of main, mpm, dune1d, ensemble, adjoint")
+                    help="comma list of main, mpm, dune1d, ensemble, adjoint, paper2d "
+                         "(paper2d: the paper's 4000x4000 runs to T, about two minutes; "
+                         "not in the default list)")
+    ap.add_argument("--paper-n", type=int, default=4000)
     ap.add_argument("--mpm-steps", type=int, default=200)
     ap.add_argument("--mpm-warmup", type=int, default=10)
     ap.add_argument("--ens-members", type=int, default=256)
@@ -378,6 +448,8 @@ def main():
         out["ensemble"] = ensemble_leg(args, sve, torch)
     if "adjoint" in legs:
         out["adjoint"] = adjoint_leg(args, sve, torch)
+    if "paper2d" in legs:
+        out["paper2d"] = paper2d_leg(args, sve, torch)
     if not args.no_cpu and "main" in legs:
         progress("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
