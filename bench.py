@@ -50,6 +50,16 @@ TRAFFIC = {"src": "7348180f4420a1c2", "rows": 0,
            "fetch_kib": 88282.5, "write_kib": 131127.9,
            "bytes_per_launch": 315.07e6}
 
+# VALU activity of the same kernel, build and workload (rocprofv3 --pmc
+# SQ_INSTS_VALU, SQ_INSTS_VALU_TRANS_F64; wavefront instructions per
+# dispatch, summed over the device).  The chip issues one wave64 VALU
+# instruction per SIMD every 4 cycles (16 for FP64 transcendentals):
+# 256 CUs x 4 SIMDs at 2.4 GHz.  Summary: profiles/k_fused_dune2000_fp64_valu.md.
+VALU = {"src": "7348180f4420a1c2", "rows": 0,
+        "insts_valu": 43853546, "insts_trans_f64": 1111242}
+SIMDS = 256 * 4
+CLOCK_HZ = 2.4e9
+
 
 def kernel_source_hash() -> str:
     """Hash of the built HIP library (its code objects hold the kernels;
@@ -428,6 +438,15 @@ def main():
         out["value"] = cells * args.steps / wall
         out["ms_per_step"] = wall * 1e3 / args.steps
         out["config"].update({"sim_time_s": t, "steps_done": ns})
+        valu = None
+        if VALU["src"] == src and args.path == "fused" and args.rows == VALU["rows"]:
+            cycles = (4 * (VALU["insts_valu"] - VALU["insts_trans_f64"])
+                      + 16 * VALU["insts_trans_f64"]) / SIMDS
+            issue_s = cycles / CLOCK_HZ
+            valu = {"lane_instructions_per_cell": VALU["insts_valu"] * 64 / cells,
+                    "fp64_transcendental_per_cell": VALU["insts_trans_f64"] * 64 / cells,
+                    "issue_us_at_2.4GHz": issue_s * 1e6,
+                    "issue_busy_frac": issue_s / per_launch_s}
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                            "traffic_unit": "HBM bytes per launch",
@@ -435,7 +454,8 @@ def main():
                                                       if traffic else None),
                            "kernel": "k_fused (update of step n + wave speeds of step n+1)",
                            "bytes_per_cell": BYTES_PER_CELL_FP64,
-                           "avg_launch_us": per_launch_s * 1e6, "kernel_src": src}
+                           "avg_launch_us": per_launch_s * 1e6, "kernel_src": src,
+                           "valu": valu}
         if not ok:
             out["error"] = "non-finite or non-positive depth after the run"
     if args.copy_calib:

@@ -43,11 +43,11 @@ __device__ __forceinline__ void iface_vjp(const Side& L, const Side& R, double g
                                           const Flux& Fb, SideAdj& Lb, SideAdj& Rb) {
     // ---- forward, keeping intermediates -------------------------------
     const bool hmaxL = L.h >= R.h;
-    const double hmax = fmax(L.h, R.h);
+    const double hmax = dmax(L.h, R.h);
     const double af2 = g * (hmax * hmax * hmax);
     const bool afL = L.aK >= R.aK;
-    const double inv_af = fmin(L.inv_aK, R.inv_aK);
-    const double a_f = fmax(L.aK, R.aK);
+    const double inv_af = dmin(L.inv_aK, R.inv_aK);
+    const double a_f = dmax(L.aK, R.aK);
     const double Hbar = 0.5 * (L.h + R.h);
     const double gH = g * Hbar;
     const double dZ = R.z - L.z;
@@ -56,8 +56,8 @@ __device__ __forceinline__ void iface_vjp(const Side& L, const Side& R, double g
     const double hbu = Hbar * u_est;
     const double fl = B_FLOOR * a_f;
     // b^2 = max(bL^2, bR^2, hbu^2, fl^2); ib names the maximum
-    const double m01 = fmax(L.b2, R.b2), m23 = fmax(hbu * hbu, fl * fl);
-    const double b2 = fmax(m01, m23);
+    const double m01 = dmax(L.b2, R.b2), m23 = fmax(hbu * hbu, fl * fl);
+    const double b2 = dmax(m01, m23);
     const int ib = m01 >= m23 ? (L.b2 >= R.b2 ? 0 : 1) : (hbu * hbu >= fl * fl ? 2 : 3);
     const double b = fsqrt(b2);
     const double A2 = af2 + b2;
@@ -67,7 +67,7 @@ __device__ __forceinline__ void iface_vjp(const Side& L, const Side& R, double g
     const double apb = a + b;
     const double c = fdiv(af2, apb);
     const bool tminL = L.tau <= R.tau;
-    const double tmin = fmin(L.tau, R.tau);
+    const double tmin = dmin(L.tau, R.tau);
     const double t3 = tmin * tmin * tmin;
     const double kappa = Hbar * t3;
     const double PL = L.Pi + a2 * L.tau;

@@ -91,6 +91,23 @@ __device__ __forceinline__ double fsqrt(double x) {
     return __builtin_fma(d, 0.5 * y, s);
 }
 
+// Maximum / minimum of two doubles as a single v_max_f64 / v_min_f64.
+// fmax and fmin compile to IEEE maxNum / minNum, which first quiet a
+// signalling NaN in every operand not provably canonical (values moved by
+// DPP, loaded, or carried around a loop): one more v_max_f64 per such
+// operand.  For non-signalling inputs the results are those of fmax / fmin
+// (a quiet NaN operand yields the other operand).
+__device__ __forceinline__ double dmax(double a, double b) {
+    double r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ double dmin(double a, double b) {
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
 // Everything a kernel needs about the model and the grid, passed by value.
 struct Model {
     int law, friction, momentum_friction;
@@ -285,40 +302,40 @@ struct Celer {
 
 __device__ __forceinline__ Celer celerities(const Side& L, const Side& R, double g) {
     Celer C;
-    const double hmax = fmax(L.h, R.h);
+    const double hmax = dmax(L.h, R.h);
     C.af2 = g * (hmax * hmax * hmax);
-    const double inv_af = fmin(L.inv_aK, R.inv_aK);       // 1 / max(aK)
-    const double a_f = fmax(L.aK, R.aK);
+    const double inv_af = dmin(L.inv_aK, R.inv_aK);       // 1 / max(aK)
+    const double a_f = dmax(L.aK, R.aK);
     C.Hbar = 0.5 * (L.h + R.h);
     C.gHbar = g * C.Hbar;
     C.dZ = R.z - L.z;
     const double u_est = 0.5 * (L.un + R.un) - (R.Pi - L.Pi + C.gHbar * C.dZ) * (0.5 * inv_af);
     const double hbu = C.Hbar * u_est;
     const double fl = B_FLOOR * a_f;
-    const double b2 = fmax(fmax(L.b2, R.b2), fmax(hbu * hbu, fl * fl));
+    const double b2 = dmax(dmax(L.b2, R.b2), fmax(hbu * hbu, fl * fl));
     C.b = fsqrt(b2);
     const double A2 = C.af2 + b2;
     C.inv_a = frsq(A2);
     C.a = A2 * C.inv_a;
     C.a2 = C.a * C.a;
     C.c = fdiv(C.af2, C.a + C.b);                          // a - b, no cancellation
-    const double tmin = fmin(L.tau, R.tau);
+    const double tmin = dmin(L.tau, R.tau);
     C.kappa = C.Hbar * (tmin * tmin * tmin);               // g H_bar / a_f^2
     return C;
 }
 
 // Largest outer wave speed max(|u_L - a tau_L|, |u_R + a tau_R|).
 __device__ __forceinline__ double iface_speed(const Side& L, const Side& R, double g) {
-    const double hmax = fmax(L.h, R.h);
+    const double hmax = dmax(L.h, R.h);
     const double af2 = g * (hmax * hmax * hmax);
-    const double inv_af = fmin(L.inv_aK, R.inv_aK);
-    const double a_f = fmax(L.aK, R.aK);
+    const double inv_af = dmin(L.inv_aK, R.inv_aK);
+    const double a_f = dmax(L.aK, R.aK);
     const double Hbar = 0.5 * (L.h + R.h);
     const double dZ = R.z - L.z;
     const double u_est = 0.5 * (L.un + R.un) - (R.Pi - L.Pi + (g * Hbar) * dZ) * (0.5 * inv_af);
     const double hbu = Hbar * u_est;
     const double fl = B_FLOOR * a_f;
-    const double b2 = fmax(fmax(L.b2, R.b2), fmax(hbu * hbu, fl * fl));
+    const double b2 = dmax(dmax(L.b2, R.b2), fmax(hbu * hbu, fl * fl));
     const double a = fsqrt(af2 + b2);
     return fmax(fabs(L.un - a * L.tau), fabs(R.un + a * R.tau));
 }
@@ -352,7 +369,7 @@ __device__ __forceinline__ unsigned iface_flux(const Side& L, const Side& R, dou
     const double tau2 = tau1 + kappa * zeta;
     const double tau3 = tau2 + D;
     const double tau4 = tau1 + D + kdz;
-    if (!(fmin(fmin(tau1, tau2), fmin(tau3, tau4)) > 0.0)) err |= ERR_POS;
+    if (!(dmin(dmin(tau1, tau2), dmin(tau3, tau4)) > 0.0)) err |= ERR_POS;
     const double sig2 = AL + c * tau1;
     const double us = sig2 + b * tau2;                     // sigma3 = u*
     const double sig4 = AR - c * tau4;

@@ -293,15 +293,15 @@ __device__ __forceinline__ void fused_tile(const Model& M, const StateView<T>& S
                         const Side Nx = side_x(PN);
                         const Side nb = next_speed_side(Nx);
                         const double s = iface_speed(Nx, nb, M.g);
-                        if (owned_lane || (lane == 0 && xghost_w)) sx = fmax(sx, s);
+                        if (owned_lane || (lane == 0 && xghost_w)) sx = dmax(sx, s);
                     }
                 }
                 if (!first_upd.value) {
                     const double s = iface_speed(c.N, Ny, M.g);
-                    if (owned_lane) sy = fmax(sy, s);
+                    if (owned_lane) sy = dmax(sy, s);
                 } else if (yghost_s) {
                     const double s = iface_speed(ghost_side_y<CL>(M, BCS, Ny, c.ag), Ny, M.g);
-                    if (owned_lane) sy = fmax(sy, s);
+                    if (owned_lane) sy = dmax(sy, s);
                 }
                 c.N = Ny;
             }
