@@ -46,6 +46,18 @@ inline int fused_tiles_y(int nx, int ny, int rows, int wave_slots) {
     T = T < ny / FUSED_MIN_ROWS ? T : ny / FUSED_MIN_ROWS;
     return T < 1 ? 1 : T;
 }
+// Tile of workgroup `id` among `nt` tiles numbered row-major (x fastest).
+// Workgroups are dispatched to the 8 XCDs in turn (id mod 8); this mapping
+// gives XCD k a contiguous band of about nt/8 tiles, so tiles that share
+// halo rows and the cache lines at their column edges run under one L2.
+// It is a bijection of [0, nt) for any nt.
+constexpr int NUM_XCD = 8;
+__device__ __forceinline__ int xcd_tile(int id, int nt) {
+    const int xcd = id % NUM_XCD, slot = id / NUM_XCD;
+    const int q = nt / NUM_XCD, r = nt % NUM_XCD;
+    return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+}
+
 constexpr int DPP_NEXT = 0x130;   // wave_shl:1 -- lane i reads lane i+1
 constexpr int DPP_PREV = 0x138;   // wave_shr:1 -- lane i reads lane i-1
 
@@ -267,6 +279,11 @@ __device__ __forceinline__ void fused_tile(const Model& M, const StateView<T>& S
                 c.pz = zn;
             }
             if (SPEEDS) {
+                // wave speeds of the new state as stored (FP32 storage rounds it)
+                hn = (double)(T)hn;
+                hun = (double)(T)hun;
+                hvn = (double)(T)hvn;
+                zn = (double)(T)zn;
                 if (xghost_e) {                      // ring lane is the east ghost
                     const double a = dpp<DPP_PREV>(hn), b = dpp<DPP_PREV>(hun);
                     const double cc = dpp<DPP_PREV>(hvn), d = dpp<DPP_PREV>(zn);
@@ -361,10 +378,12 @@ k_fused(Model M, StateView<T> S, StateView<T> D, const double* __restrict__ Agf,
         int n, double cfl, double t_end, double fixed_dt, int tiles_y) {
     if (ctrl->err) return;
     const StepTime st = step_time(M, ctrl, n, cfl, t_end, fixed_dt);
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) step_bookkeeping(ctrl, n, st);
+    if (blockIdx.x == 0 && threadIdx.x == 0) step_bookkeeping(ctrl, n, st);
+    const int tiles_x = (M.nx + FUSED_OWN - 1) / FUSED_OWN;
+    const int t = xcd_tile(blockIdx.x, tiles_x * tiles_y);
     int j0, jend;
-    tile_rows(M.ny, tiles_y, blockIdx.y, j0, jend);
-    fused_tile<T, CL, SPEEDS>(M, S, D, Agf, ctrl, n, st, blockIdx.x, j0, jend);
+    tile_rows(M.ny, tiles_y, t / tiles_x, j0, jend);
+    fused_tile<T, CL, SPEEDS>(M, S, D, Agf, ctrl, n, st, t % tiles_x, j0, jend);
 }
 
 // tiles_y: number of row tiles (fused_tiles_y), 1 <= tiles_y <= ny.
@@ -373,7 +392,7 @@ void launch_fused_rows(const Model& M, StateView<T> S, StateView<T> D, const dou
                        Ctrl* ctrl, int n, double cfl, double t_end, double fixed_dt, int tiles_y,
                        hipStream_t stream) {
     const int tiles_x = (M.nx + FUSED_OWN - 1) / FUSED_OWN;
-    const dim3 grid(tiles_x, tiles_y);
+    const dim3 grid(tiles_x * tiles_y);
     const int cl = closure_class(M);
     const bool sp = !(fixed_dt > 0.0);
     auto kern = cl == CL_GRASS3 ? (sp ? k_fused<T, CL_GRASS3, true> : k_fused<T, CL_GRASS3, false>)

@@ -92,7 +92,7 @@ def test_mpm_channel_8192x2048_full_grid(sve, storage, tol):
             O.BC(O.BC_FREE))
     o = O.Oracle2D(h, hu, hv, zb, dx, dy, po, obcs, storage=storage)
     o.step(2, 0.5)
-    assert t == pytest.approx(o.t, rel=tol)
+    assert t == pytest.approx(o.t, rel=TOL64)       # dt from the state as stored
     assert_fields_close(fields, o.state, tol)
     if storage == "fp32":
         for a in fields:

@@ -124,7 +124,9 @@ def test_mpm_fp32_storage(sve, path):
     bcs = [sve.BC(sve.BC_INFLOW, 0.5, 2.0, 0.0), sve.BC(sve.BC_FREE),
            sve.BC(sve.BC_FREE), sve.BC(sve.BC_FREE)]
     f, t, dtl, ns, o = run_pair(sve, case, mpm(sve), bcs, 80, storage="fp32", path=PATHS[path])
-    assert t == pytest.approx(o.t, rel=TOL32)
+    # every dt comes from the wave speeds of the state as stored (rounded to
+    # float32) on both sides, so the times agree to FP64 rounding
+    assert t == pytest.approx(o.t, rel=TOL64)
     assert_fields_close(f, o.state, TOL32)
     for a in f:
         assert np.array_equal(a, a.astype(np.float32).astype(np.float64))
