@@ -327,10 +327,11 @@ __device__ __forceinline__ void project_vjp_grass(const Model& M, double h, doub
     } else if (M.mg_is1) {
         p = 1.0; dp_dw = 0.0; r = w > 0.0 ? 1.0 / w : 0.0; dr_dw = w > 0.0 ? -r / w : 0.0;
     } else if (w > 0.0) {
+        // the forward closure's evaluation: r = w^((m-3)/2), p = r w
         const double e = 0.5 * (m - 1.0);
-        p = pow(w, e);
-        dp_dw = e * p / w;
-        r = p / w;
+        r = gpow(w, 0.5 * (m - 3.0));
+        p = r * w;
+        dp_dw = e * r;
         dr_dw = (e - 1.0) * r / w;
     } else {
         p = 0.0; dp_dw = 0.0; r = 0.0; dr_dw = 0.0;

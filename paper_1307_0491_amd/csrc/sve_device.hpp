@@ -91,6 +91,65 @@ __device__ __forceinline__ double fsqrt(double x) {
     return __builtin_fma(d, 0.5 * y, s);
 }
 
+// w^p for finite w > 0 and |p| <= 2 (the Grass law's |U|^(m_g - 1)):
+// exp(p ln w) with
+//   ln w = e ln2 + 2 atanh(s), w = 2^e m, m in [sqrt(1/2), sqrt(2)),
+//          s = (m - 1)/(m + 1), |s| <= 0.1716, atanh by its odd Taylor
+//          series to s^21 (truncation below 2^-55 relative);
+//   exp(y) = 2^k exp(r), k = rint(y / ln2), |r| <= ln2 / 2, exp(r) by its
+//          Taylor series to r^13 (truncation below 2^-57);
+// ln2 is split into a 42-bit head and a tail so that k ln2 and e ln2 are
+// formed without rounding error.  The result is within a few ulp when
+// |p ln w| <= 10 (velocities between 1e-3 and 1e2 m/s); beyond that the
+// rounding of y adds about |p ln w| ulp.  One reciprocal (v_rcp_f64) and
+// about 50 other instructions, against some 200 for the library pow, whose
+// extra precision this closure does not need.
+__device__ __forceinline__ double gpow(double w, double p) {
+    constexpr double LN2_HI = 0x1.62e42fefa3800p-1;   // 42 significant bits
+    constexpr double LN2_LO = 0x1.ef35793c76730p-45;  // ln2 - LN2_HI
+    constexpr double INV_LN2 = 1.4426950408889634;
+    double m = __builtin_amdgcn_frexp_mant(w);        // [1/2, 1)
+    int e = __builtin_amdgcn_frexp_exp(w);
+    const bool low = m < 0.7071067811865476;
+    m = low ? 2.0 * m : m;
+    e = low ? e - 1 : e;
+    const double s = fdiv(m - 1.0, m + 1.0);
+    const double z = s * s;
+    double t = 1.0 / 21.0;
+    t = __builtin_fma(t, z, 1.0 / 19.0);
+    t = __builtin_fma(t, z, 1.0 / 17.0);
+    t = __builtin_fma(t, z, 1.0 / 15.0);
+    t = __builtin_fma(t, z, 1.0 / 13.0);
+    t = __builtin_fma(t, z, 1.0 / 11.0);
+    t = __builtin_fma(t, z, 1.0 / 9.0);
+    t = __builtin_fma(t, z, 1.0 / 7.0);
+    t = __builtin_fma(t, z, 1.0 / 5.0);
+    t = __builtin_fma(t, z, 1.0 / 3.0);
+    t *= z;                                           // z/3 + z^2/5 + ... + z^10/21
+    const double s2 = 2.0 * s;
+    const double lnm = __builtin_fma(s2, t, s2);      // 2 atanh(s) = ln m
+    const double de = (double)e;
+    const double lnw = de * LN2_HI + __builtin_fma(de, LN2_LO, lnm);
+    const double y = p * lnw;
+    const double kf = __builtin_rint(y * INV_LN2);
+    const double r = __builtin_fma(-kf, LN2_LO, __builtin_fma(-kf, LN2_HI, y));
+    double q = 1.0 / 6227020800.0;                    // 1/13!
+    q = __builtin_fma(q, r, 1.0 / 479001600.0);       // 1/12!
+    q = __builtin_fma(q, r, 1.0 / 39916800.0);
+    q = __builtin_fma(q, r, 1.0 / 3628800.0);
+    q = __builtin_fma(q, r, 1.0 / 362880.0);
+    q = __builtin_fma(q, r, 1.0 / 40320.0);
+    q = __builtin_fma(q, r, 1.0 / 5040.0);
+    q = __builtin_fma(q, r, 1.0 / 720.0);
+    q = __builtin_fma(q, r, 1.0 / 120.0);
+    q = __builtin_fma(q, r, 1.0 / 24.0);
+    q = __builtin_fma(q, r, 1.0 / 6.0);
+    q = __builtin_fma(q, r, 0.5);
+    q = __builtin_fma(q, r, 1.0);
+    q = __builtin_fma(q, r, 1.0);
+    return __builtin_amdgcn_ldexp(q, (int)kf);
+}
+
 // Maximum / minimum of two doubles as a single v_max_f64 / v_min_f64.
 // fmax and fmin compile to IEEE maxNum / minNum, which first quiet a
 // signalling NaN in every operand not provably canonical (values moved by
@@ -193,7 +252,7 @@ __device__ __forceinline__ void threshold_law(int law, double theta, double tc,
         F = 12.0 * sq * e;
         dF = 12.0 * (e / (2.0 * sq) + sq);
     } else {  // LAW_RIBBERINK
-        const double p = pow(e, 0.65);
+        const double p = gpow(e, 0.65);
         F = 11.0 * e * p;
         dF = 18.15 * p;
     }
@@ -235,17 +294,19 @@ __device__ __forceinline__ void closure(const Model& M, double h, double u,
             bx = Ag;
             by = Ag;
         } else {
-            const double p = pow(w, 0.5 * (M.mg - 1.0));
-            qx = Ag * p * u;
-            qy = Ag * p * v;
-            if (w > 0.0) {
-                const double r = 1.0 / w;
-                bx = Ag * p * (M.mg * uu + vv) * r;
-                by = Ag * p * (uu + M.mg * vv) * r;
-            } else {
-                bx = M.mg_is1 ? Ag : 0.0;
-                by = bx;
-            }
+            // r = |U|^(m-3) = w^((m-3)/2), so |U|^(m-1) = r w and
+            // beta_x = A_g r (m u^2 + v^2).  At U = 0: q = 0, and beta = A_g
+            // for m = 1 (q = A_g U), else 0.  Speeds below 1e-150 count as
+            // rest (q and the m > 1 beta are then below A_g 1e-150, and r
+            // stays finite).
+            const bool moving = w > 1e-300;
+            const double r = moving ? gpow(w, 0.5 * (M.mg - 3.0)) : 0.0;
+            const double Ap = Ag * (r * w);
+            qx = Ap * u;
+            qy = Ap * v;
+            const double b0 = M.mg_is1 ? Ag : 0.0;
+            bx = moving ? Ag * r * (M.mg * uu + vv) : b0;
+            by = moving ? Ag * r * (uu + M.mg * vv) : b0;
         }
         return;
     }
