@@ -2,11 +2,12 @@
 // whole state and runs all requested steps in one launch (the 1D dune of
 // the paper has 1000 cells: a grid-wide pass per step would be launch-bound).
 //
-// Per step: interface fluxes into LDS, barrier, cell update in place,
-// barrier, outer wave speeds of the new state reduced in LDS into the next
-// time step.  The loop ends after n steps, or early when t reaches t_end
-// (the remaining steps would leave the state unchanged) or on an error (the
-// state before the failing step is kept).
+// Per step: one pass over the interfaces gives the fluxes (into LDS) and
+// the outer wave speeds of the current state (reduced in LDS into the time
+// step), barrier, cell update into registers, barrier (error check), new
+// state into LDS, barrier.  The loop ends after n steps, or early when t
+// reaches t_end (the remaining steps would leave the state unchanged) or on
+// an error (the state before the failing step is kept).
 #pragma once
 
 #include "sve_context.hpp"
@@ -98,7 +99,8 @@ k_resident_1d(Model M, StateView<T> S, StateView<T> D, const double* __restrict_
     __syncthreads();
     const bool cfl_mode = !(fixed_dt > 0.0);
     double t = ctrl->t[n0 % 3];
-    double S_next = cfl_mode ? u64_as_double(ctrl->smax[n0 % 3][0]) : 0.0;
+    double S_cur = 0.0;                              // outer wave speed of the state in LDS
+    bool S_known = false;
     double dt_last = ctrl->dt_last;
     int done = 0;
     unsigned err = 0u;
@@ -108,9 +110,35 @@ k_resident_1d(Model M, StateView<T> S, StateView<T> D, const double* __restrict_
             dt_last = 0.0;
             break;
         }
+        // fluxes and outer wave speeds of the current state
+        unsigned e = 0u;
+        double s = 0.0;
+        for (int m = threadIdx.x; m <= nx; m += RES_BLOCK) {
+            double h, hu, z, ag;
+            res_cell(M, L, Agf, m - 1, h, hu, z, ag);
+            const Cell A = project<CL>(M, h, hu, 0.0, z, ag);
+            res_cell(M, L, Agf, m, h, hu, z, ag);
+            const Cell B = project<CL>(M, h, hu, 0.0, z, ag);
+            Flux F;
+            double sp;
+            e |= iface_flux(side_x(A), side_x(B), M.g, F, sp);
+            s = dmax(s, sp);
+            L.Fh[m] = F.Fh;
+            L.FL[m] = F.FhuL;
+            L.FR[m] = F.FhuR;
+            L.Fz[m] = F.Fz;
+        }
+        if (cfl_mode) {
+            s = wave_max(s);
+            if ((threadIdx.x & 63) == 0) L.red[threadIdx.x >> 6] = s;
+        }
+        __syncthreads();
         double dt, tnew;
         if (cfl_mode) {
-            dt = cfl * M.dx / S_next;
+            S_cur = 0.0;
+            for (int w = 0; w < RES_BLOCK / 64; ++w) S_cur = fmax(S_cur, L.red[w]);
+            S_known = true;
+            dt = cfl * M.dx / S_cur;
             tnew = t + dt;
             if (t_end > 0.0 && dt >= t_end - t) {
                 dt = t_end - t;
@@ -120,21 +148,6 @@ k_resident_1d(Model M, StateView<T> S, StateView<T> D, const double* __restrict_
             dt = fixed_dt;
             tnew = t + dt;
         }
-        unsigned e = 0u;
-        for (int m = threadIdx.x; m <= nx; m += RES_BLOCK) {
-            double h, hu, z, ag;
-            res_cell(M, L, Agf, m - 1, h, hu, z, ag);
-            const Cell A = project<CL>(M, h, hu, 0.0, z, ag);
-            res_cell(M, L, Agf, m, h, hu, z, ag);
-            const Cell B = project<CL>(M, h, hu, 0.0, z, ag);
-            Flux F;
-            e |= iface_flux(side_x(A), side_x(B), M.g, F);
-            L.Fh[m] = F.Fh;
-            L.FL[m] = F.FhuL;
-            L.FR[m] = F.FhuR;
-            L.Fz[m] = F.Fz;
-        }
-        __syncthreads();
         const double lx = dt / M.dx;
         double nh[RES_PER_THREAD], nhu[RES_PER_THREAD], nz[RES_PER_THREAD];
         int c = 0;
@@ -164,8 +177,10 @@ k_resident_1d(Model M, StateView<T> S, StateView<T> D, const double* __restrict_
         __syncthreads();
         t = tnew;
         dt_last = dt;
-        if (cfl_mode) S_next = res_max_speed<CL>(M, L, Agf);
+        S_known = false;
     }
+    // outer wave speed of the state left in LDS, for the next call's first step
+    if (cfl_mode && !S_known) S_cur = res_max_speed<CL>(M, L, Agf);
     // write back the last good state into the buffer the host expects
     const StateView<T>& out = (done & 1) ? D : S;
     for (int i = threadIdx.x; i < nx; i += RES_BLOCK) {
@@ -181,7 +196,7 @@ k_resident_1d(Model M, StateView<T> S, StateView<T> D, const double* __restrict_
         }
         ctrl->t[nend % 3] = t;
         ctrl->dt_last = dt_last;
-        ctrl->smax[nend % 3][0] = cfl_mode ? double_as_u64(S_next) : 0ull;
+        ctrl->smax[nend % 3][0] = cfl_mode ? double_as_u64(S_cur) : 0ull;
         ctrl->smax[nend % 3][1] = 0ull;
         for (int k = 1; k < 3; ++k) {
             ctrl->smax[(nend + k) % 3][0] = 0ull;
