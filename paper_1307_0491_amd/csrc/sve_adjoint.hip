@@ -117,7 +117,7 @@ k_adjoint_march(Model M, StateView<double> U, const double* __restrict__ Agf,
             if (r > j0) {                            // row r-1 is complete
                 add_y(acc, Lb);
                 double hb, hub, hvb, zb, Agb;
-                project_vjp_grass(M, hp, hup, hvp, agp, acc, hb, hub, hvb, zb, Agb);
+                project_vjp_grass<CL>(M, hp, hup, hvp, agp, acc, hb, hub, hvb, zb, Agb);
                 if (owned) {
                     const long long k = (long long)(r - 1) * M.nx + col;
                     Lout.h[k] = lp.h + hb;

@@ -310,41 +310,45 @@ __device__ __forceinline__ void iface_vjp(const Side& L, const Side& R, double g
 }
 
 // Reverse of the projection of a cell with the Grass closure: maps the
-// adjoints of the projected quantities to (h, hu, hv, z_b, A_g).
+// adjoints of the projected quantities to (h, hu, hv, z_b, A_g).  CL is the
+// closure family of the forward kernel (CL_GRASS3, CL_GRASS1 or CL_GRASSM).
+template <int CL>
 __device__ __forceinline__ void project_vjp_grass(const Model& M, double h, double hu, double hv,
                                                   double Ag, const CellAdj& cb, double& hb,
                                                   double& hub, double& hvb, double& zb,
                                                   double& Agb) {
     const double g = M.g;
-    const double tau = 1.0 / h;
+    const double tau = frcp(h);
     const double u = hu * tau, v = hv * tau;
     const double uu = u * u, vv = v * v, w = uu + vv;
-    const double m = M.mg;
+    const double m = CL == CL_GRASS3 ? 3.0 : CL == CL_GRASS1 ? 1.0 : M.mg;
     // closure values and partial derivatives (q = Ag p (u, v), beta = Ag r N)
     double p, dp_dw, r, dr_dw;
-    if (M.mg_is3) {
+    if (CL == CL_GRASS3) {
         p = w; dp_dw = 1.0; r = 1.0; dr_dw = 0.0;
-    } else if (M.mg_is1) {
-        p = 1.0; dp_dw = 0.0; r = w > 0.0 ? 1.0 / w : 0.0; dr_dw = w > 0.0 ? -r / w : 0.0;
-    } else if (w > 0.0) {
+    } else if (CL == CL_GRASS1) {
+        p = 1.0; dp_dw = 0.0;
+        const double iw = w > 0.0 ? frcp(w) : 0.0;
+        r = iw; dr_dw = -iw * iw;
+    } else if (w > 1e-300) {
         // the forward closure's evaluation: r = w^((m-3)/2), p = r w
         const double e = 0.5 * (m - 1.0);
         r = gpow(w, 0.5 * (m - 3.0));
         p = r * w;
         dp_dw = e * r;
-        dr_dw = (e - 1.0) * r / w;
+        dr_dw = (e - 1.0) * r * frcp(w);
     } else {
         p = 0.0; dp_dw = 0.0; r = 0.0; dr_dw = 0.0;
     }
     const double Nx = m * uu + vv, Ny = uu + m * vv;
     double bx, by;
-    if (M.mg_is3) { bx = Ag * (3.0 * uu + vv); by = Ag * (uu + 3.0 * vv); }
-    else if (M.mg_is1) { bx = Ag; by = Ag; }
+    if (CL == CL_GRASS3) { bx = Ag * (3.0 * uu + vv); by = Ag * (uu + 3.0 * vv); }
+    else if (CL == CL_GRASS1) { bx = Ag; by = Ag; }
     else { bx = Ag * r * Nx; by = Ag * r * Ny; }
     const double dqx_du = Ag * (p + 2.0 * uu * dp_dw), dqx_dv = Ag * 2.0 * u * v * dp_dw;
     const double dqy_du = dqx_dv, dqy_dv = Ag * (p + 2.0 * vv * dp_dw);
     double dbx_du, dbx_dv, dby_du, dby_dv, dbx_dA, dby_dA;
-    if (M.mg_is1) {
+    if (CL == CL_GRASS1) {
         dbx_du = dbx_dv = dby_du = dby_dv = 0.0;
         dbx_dA = dby_dA = 1.0;
     } else {
@@ -352,8 +356,8 @@ __device__ __forceinline__ void project_vjp_grass(const Model& M, double h, doub
         dbx_dv = Ag * (dr_dw * 2.0 * v * Nx + r * 2.0 * v);
         dby_du = Ag * (dr_dw * 2.0 * u * Ny + r * 2.0 * u);
         dby_dv = Ag * (dr_dw * 2.0 * v * Ny + r * 2.0 * m * v);
-        dbx_dA = M.mg_is3 ? 3.0 * uu + vv : r * Nx;
-        dby_dA = M.mg_is3 ? uu + 3.0 * vv : r * Ny;
+        dbx_dA = CL == CL_GRASS3 ? 3.0 * uu + vv : r * Nx;
+        dby_dA = CL == CL_GRASS3 ? uu + 3.0 * vv : r * Ny;
     }
     // b2 = hu^2 + g h^2 beta
     const double gh2 = g * h * h;
@@ -371,7 +375,7 @@ __device__ __forceinline__ void project_vjp_grass(const Model& M, double h, doub
     double taub = cb.tau + ub * hu + vb * hv;
     // Pi = g h^2 / 2 ; aK = h sqrt(g h) ; tau = 1 / h
     hb += cb.Pi * g * h;
-    hb += cb.aK * 1.5 * sqrt(g * h);
+    hb += cb.aK * 1.5 * fsqrt(g * h);
     hb -= taub * tau * tau;
     zb = cb.z;
 }
