@@ -25,6 +25,11 @@ struct CellAdj {
     double h, tau, u, v, Pi, z, qx, qy, bx2, by2, aK;
 };
 
+// a += x where c holds.  Written as a select so that conditional
+// accumulations into one of several adjoints compile to selects, not to a
+// dynamically indexed temporary array in scratch memory.
+__device__ __forceinline__ void add_if(double& a, bool c, double x) { a += c ? x : 0.0; }
+
 __device__ __forceinline__ void add_x(CellAdj& c, const SideAdj& s) {
     c.h += s.h; c.tau += s.tau; c.u += s.un; c.v += s.ut; c.Pi += s.Pi; c.z += s.z;
     c.qx += s.q; c.bx2 += s.b2; c.aK += s.aK;
@@ -127,7 +132,8 @@ __device__ __forceinline__ void iface_vjp(const Side& L, const Side& R, double g
     const double O0b = Fb.Fz;
     double Fhb = Fb.Fh + Fb.Fht * vt0;
     const double vt0b = Fb.Fht * Fh;
-    if (right) Rb.ut += vt0b; else Lb.ut += vt0b;
+    add_if(Rb.ut, right, vt0b);
+    add_if(Lb.ut, !right, vt0b);
     // P0 = u0 F_h + Pi0
     double u0b = P0b * Fh;
     Fhb += P0b * u0;
@@ -142,19 +148,26 @@ __device__ __forceinline__ void iface_vjp(const Side& L, const Side& R, double g
     if (outer) {
         double tauOb = tau0b;
         // uO = Aside + sa tauO
-        if (right) { ARb += u0b; ab -= u0b * tauO; } else { ALb += u0b; ab += u0b * tauO; }
+        add_if(ARb, right, u0b);
+        add_if(ALb, !right, u0b);
+        ab += (right ? -u0b : u0b) * tauO;
         tauOb += u0b * (right ? -a : a);
         // PiO = Pside - a2 tauO
-        if (right) PRb += Pi0b; else PLb += Pi0b;
+        add_if(PRb, right, Pi0b);
+        add_if(PLb, !right, Pi0b);
         a2b -= Pi0b * tauO;
         tauOb -= Pi0b * a2;
-        if (srcO == 5) Rb.tau += tauOb;
-        else if (srcO == 4) tau4b += tauOb;
-        else if (srcO == 1) tau1b += tauOb;
-        else Lb.tau += tauOb;
-        if (right) { Rb.z += Z0b; Rb.q += O0b; } else { Lb.z += Z0b; Lb.q += O0b; }
+        add_if(Rb.tau, srcO == 5, tauOb);
+        add_if(tau4b, srcO == 4, tauOb);
+        add_if(tau1b, srcO == 1, tauOb);
+        add_if(Lb.tau, srcO == 0, tauOb);
+        add_if(Rb.z, right, Z0b);
+        add_if(Rb.q, right, O0b);
+        add_if(Lb.z, !right, Z0b);
+        add_if(Lb.q, !right, O0b);
     } else {
-        if (l3) tau3b += tau0b; else tau2b += tau0b;
+        add_if(tau3b, l3, tau0b);
+        add_if(tau2b, !l3, tau0b);
         usb += u0b;
         PLb += Pi0b;
         a2b -= Pi0b * tau2;
@@ -260,7 +273,8 @@ __device__ __forceinline__ void iface_vjp(const Side& L, const Side& R, double g
     // kappa = Hbar tmin^3
     double Hbarb = kappab * t3;
     const double tminb = kappab * 3.0 * Hbar * tmin * tmin;
-    if (tminL) Lb.tau += tminb; else Rb.tau += tminb;
+    add_if(Lb.tau, tminL, tminb);
+    add_if(Rb.tau, !tminL, tminb);
     // c = af2 / (a + b)
     const double inv_apb = frcp(apb);
     double af2b = cb * inv_apb;
@@ -275,11 +289,10 @@ __device__ __forceinline__ void iface_vjp(const Side& L, const Side& R, double g
     af2b += A2b;
     double b2b = A2b + 0.5 * bb * frcp(b);
     // b2 = max(bL2, bR2, hbu^2, fl^2)
-    double hbub = 0.0, flb = 0.0;
-    if (ib == 0) Lb.b2 += b2b;
-    else if (ib == 1) Rb.b2 += b2b;
-    else if (ib == 2) hbub = 2.0 * hbu * b2b;
-    else flb = 2.0 * fl * b2b;
+    add_if(Lb.b2, ib == 0, b2b);
+    add_if(Rb.b2, ib == 1, b2b);
+    const double hbub = ib == 2 ? 2.0 * hbu * b2b : 0.0;
+    const double flb = ib == 3 ? 2.0 * fl * b2b : 0.0;
     double a_fb = B_FLOOR * flb;
     // hbu = Hbar u_est
     Hbarb += hbub * u_est;
@@ -296,7 +309,8 @@ __device__ __forceinline__ void iface_vjp(const Side& L, const Side& R, double g
     dZb += wb * gH;
     // inv_af = 1 / a_f ; a_f = max(aK)
     a_fb -= inv_afb * inv_af * inv_af;
-    if (afL) Lb.aK += a_fb; else Rb.aK += a_fb;
+    add_if(Lb.aK, afL, a_fb);
+    add_if(Rb.aK, !afL, a_fb);
     // dZ = zR - zL
     Rb.z += dZb;
     Lb.z -= dZb;
@@ -306,7 +320,8 @@ __device__ __forceinline__ void iface_vjp(const Side& L, const Side& R, double g
     Rb.h += 0.5 * Hbarb;
     // af2 = g hmax^3
     const double hmaxb = af2b * 3.0 * g * hmax * hmax;
-    if (hmaxL) Lb.h += hmaxb; else Rb.h += hmaxb;
+    add_if(Lb.h, hmaxL, hmaxb);
+    add_if(Rb.h, !hmaxL, hmaxb);
 }
 
 // Reverse of the projection of a cell with the Grass closure: maps the
