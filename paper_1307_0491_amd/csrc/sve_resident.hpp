@@ -16,7 +16,9 @@
 namespace sve {
 
 constexpr int RES_BLOCK = 1024;
-constexpr int RES_PER_THREAD = 8;                 // cells per thread (registers)
+// cells per thread: the LDS of one workgroup (160 KiB, 56 B per cell) holds
+// at most 2922 cells, so three per thread cover every grid that fits
+constexpr int RES_PER_THREAD = 3;
 constexpr int RES_NMAX = RES_BLOCK * RES_PER_THREAD;
 
 // LDS layout, carved from dynamic shared memory sized for nx.
@@ -149,9 +151,13 @@ k_resident_1d(Model M, StateView<T> S, StateView<T> D, const double* __restrict_
             tnew = t + dt;
         }
         const double lx = dt / M.dx;
+        // new state in registers (constant indices after unrolling) until
+        // the step is known to be free of errors
         double nh[RES_PER_THREAD], nhu[RES_PER_THREAD], nz[RES_PER_THREAD];
-        int c = 0;
-        for (int i = threadIdx.x; i < nx; i += RES_BLOCK, ++c) {
+#pragma unroll
+        for (int c = 0; c < RES_PER_THREAD; ++c) {
+            const int i = threadIdx.x + c * RES_BLOCK;
+            if (i >= nx) continue;
             double hn = L.h[i] - lx * (L.Fh[i + 1] - L.Fh[i]);
             double hun = L.hu[i] - lx * (L.FL[i + 1] - L.FR[i]);
             double zn = L.z[i] - lx * (L.Fz[i + 1] - L.Fz[i]);
@@ -168,8 +174,10 @@ k_resident_1d(Model M, StateView<T> S, StateView<T> D, const double* __restrict_
         __syncthreads();
         err = *L.err;
         if (err) break;                              // keep the state before this step
-        c = 0;
-        for (int i = threadIdx.x; i < nx; i += RES_BLOCK, ++c) {
+#pragma unroll
+        for (int c = 0; c < RES_PER_THREAD; ++c) {
+            const int i = threadIdx.x + c * RES_BLOCK;
+            if (i >= nx) continue;
             L.h[i] = (double)(T)nh[c];
             L.hu[i] = (double)(T)nhu[c];
             L.z[i] = (double)(T)nz[c];
