@@ -159,8 +159,10 @@ const char *sve_strerror(int code);
  *   SVE_PATH_FUSED   one kernel per step: update of step n and
  *                    the wave speeds of step n+1 in a single pass;
  *   SVE_PATH_SPLIT   two kernels per step (update, then wave speeds);
- *   SVE_PATH_RESIDENT (1D only, nx <= 8192) one workgroup keeps the whole
- *                    grid in LDS and runs all n steps in one launch;
+ *   SVE_PATH_RESIDENT (1D only, grids whose state and fluxes fit in one
+ *                    workgroup's LDS: 56 bytes per cell, nx <= 2922 on
+ *                    gfx950) one workgroup keeps the whole grid in LDS and
+ *                    runs all n steps in one launch;
  *   SVE_PATH_RESIDUAL (2D CFL steps; 1D and fixed-dt steps run as FUSED)
  *                    one kernel per step that applies U - dt R of the
  *                    previous pass and solves the new state's interfaces
