@@ -66,18 +66,20 @@ __device__ __forceinline__ SideAdj prev_lane(const SideAdj& s) {
 // adjoint seed of an interface's fluxes comes from lambda^{n+1} of its two
 // cells: U' = U - dt/dx (F^L_{i+1/2} - F^R_{i-1/2}) - ...
 //
-// One wavefront per workgroup, two per SIMD (the register budget is 256; a
-// few values spill).  Workgroup (tx, ty) runs tile (tx, ty) of a split of
-// the rows into tiles_y tiles (tile_rows).
+// One wavefront per workgroup, two per SIMD (the register budget is 256).
+// Workgroup id runs tile xcd_tile(id) of the tiles_x x tiles_y split
+// (row-major; rows by tile_rows), so each XCD gets a contiguous band.
 template <int CL>
 __global__ void __launch_bounds__(64, 2)
 k_adjoint_march(Model M, StateView<double> U, const double* __restrict__ Agf,
                 StateView<double> Lin, StateView<double> Lout, double* __restrict__ gAg,
                 double dt, int tiles_y) {
     const int lane = threadIdx.x & 63;
-    const int i0 = blockIdx.x * FUSED_OWN;
+    const int tiles_x = (M.nx + FUSED_OWN - 1) / FUSED_OWN;
+    const int t = xcd_tile(blockIdx.x, tiles_x * tiles_y);
+    const int i0 = (t % tiles_x) * FUSED_OWN;
     int j0, jend;                                    // owned rows [j0, jend)
-    tile_rows(M.ny, tiles_y, blockIdx.y, j0, jend);
+    tile_rows(M.ny, tiles_y, t / tiles_x, j0, jend);
     const int l_last = min(FUSED_OWN, M.nx - i0);    // owned lanes 1..l_last
     const bool owned = lane >= 1 && lane <= l_last;
     const int col = i0 - 1 + lane;
@@ -252,7 +254,7 @@ int reverse_step(sve_ctx* c, double* U, double* lin, double* lout, double* gAg, 
                                 : k_adjoint_march<CL_GRASSM>;
     const int tiles_x = (c->M.nx + FUSED_OWN - 1) / FUSED_OWN;
     const int tiles_y = fused_tiles_y(c->M.nx, c->M.ny, c->adj_ty, c->wave_slots);
-    hipLaunchKernelGGL(kern, dim3(tiles_x, tiles_y), dim3(64), 0, c->stream, c->M,
+    hipLaunchKernelGGL(kern, dim3(tiles_x * tiles_y), dim3(64), 0, c->stream, c->M,
                        view(U, c->pitch), (const double*)c->Ag, view(lin, c->pitch),
                        view(lout, c->pitch), gAg, dt, tiles_y);
     return hipGetLastError() == hipSuccess ? SVE_OK : SVE_ERR_HIP;

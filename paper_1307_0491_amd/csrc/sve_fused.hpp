@@ -370,8 +370,8 @@ __device__ __forceinline__ void fused_tile(const Model& M, const StateView<T>& S
     }
 }
 
-// One wavefront per workgroup: workgroup (tx, ty) runs tile (tx, ty) of a
-// split of the rows into tiles_y tiles (tile_rows).
+// One wavefront per workgroup: workgroup id runs tile xcd_tile(id) of the
+// tiles_x x tiles_y split (row-major; rows by tile_rows).
 template <typename T, int CL, bool SPEEDS>
 __global__ void __launch_bounds__(64, FUSED_WAVES_PER_SIMD)
 k_fused(Model M, StateView<T> S, StateView<T> D, const double* __restrict__ Agf, Ctrl* ctrl,

@@ -188,8 +188,8 @@ __device__ __forceinline__ void resid_tile(const Model& M, const StateView<T>& S
     }
 }
 
-// One wavefront per workgroup; workgroup (tx, ty) runs tile (tx, ty) of the
-// row split (tile_rows).  INIT: residual and wave speeds of the state in S
+// One wavefront per workgroup; workgroup id runs tile xcd_tile(id) of the
+// tiles_x x tiles_y split (row-major; rows by tile_rows).  INIT: residual and wave speeds of the state in S
 // (step n's slot); otherwise step n, whose wave speeds are in slot n%3.
 template <typename T, int CL, bool INIT>
 __global__ void __launch_bounds__(64, FUSED_WAVES_PER_SIMD)
@@ -201,17 +201,19 @@ k_resid(Model M, StateView<T> S, StateView<double> RS, StateView<T> D, StateView
     int slot = n % 3;
     if (!INIT) {
         const StepTime st = step_time(M, ctrl, n, cfl, t_end, 0.0);
-        if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) step_bookkeeping(ctrl, n, st);
+        if (blockIdx.x == 0 && threadIdx.x == 0) step_bookkeeping(ctrl, n, st);
         dt = st.dt;
         slot = (n + 1) % 3;
-    } else if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    } else if (blockIdx.x == 0 && threadIdx.x == 0) {
         // the first step kernel accumulates into slot (n+1)%3
         ctrl->smax[(n + 1) % 3][0] = 0ull;
         ctrl->smax[(n + 1) % 3][1] = 0ull;
     }
+    const int tiles_x = (M.nx + FUSED_OWN - 1) / FUSED_OWN;
+    const int t = xcd_tile(blockIdx.x, tiles_x * tiles_y);
     int j0, jend;
-    tile_rows(M.ny, tiles_y, blockIdx.y, j0, jend);
-    resid_tile<T, CL, INIT>(M, S, RS, D, RD, Agf, ctrl, n, dt, slot, blockIdx.x, j0, jend);
+    tile_rows(M.ny, tiles_y, t / tiles_x, j0, jend);
+    resid_tile<T, CL, INIT>(M, S, RS, D, RD, Agf, ctrl, n, dt, slot, t % tiles_x, j0, jend);
 }
 
 template <typename T, bool INIT>
@@ -224,7 +226,7 @@ void launch_resid(const Model& M, StateView<T> S, StateView<double> RS, StateVie
               : cl == CL_GRASS1 ? k_resid<T, CL_GRASS1, INIT>
               : cl == CL_GRASSM ? k_resid<T, CL_GRASSM, INIT>
                                 : k_resid<T, CL_THRESH, INIT>;
-    hipLaunchKernelGGL(kern, dim3(tiles_x, tiles_y), dim3(64), 0, stream, M, S, RS, D, RD, Ag,
+    hipLaunchKernelGGL(kern, dim3(tiles_x * tiles_y), dim3(64), 0, stream, M, S, RS, D, RD, Ag,
                        ctrl, n, cfl, t_end, tiles_y);
 }
 

@@ -132,6 +132,23 @@ def test_mpm_fp32_storage(sve, path):
         assert np.array_equal(a, a.astype(np.float32).astype(np.float64))
 
 
+@pytest.mark.parametrize("mg", [1.3, 2.5, 3.7])
+def test_general_exponent_wide_speed_range(sve, mg):
+    """The general-exponent closure (|U|^(m_g-1) by exp and log series on
+    the GPU, the library power in the oracle) on speeds from 1e-7 to 4 m/s
+    in random directions: |(m_g-3)/2 ln |U|^2| reaches 27."""
+    case = dune2d_case(90, 70)
+    rng = np.random.default_rng(11)
+    speed = 10.0 ** rng.uniform(-7.0, 0.6, case["h"].shape)
+    ang = rng.uniform(0.0, 2.0 * np.pi, case["h"].shape)
+    case["hu"] = case["h"] * speed * np.cos(ang)
+    case["hv"] = case["h"] * speed * np.sin(ang)
+    f, t, dtl, ns, o = run_pair(sve, case, grass(sve, Ag=1e-2, mg=mg), per(sve), 20)
+    assert ns == 20
+    assert t == pytest.approx(o.t, rel=TOL64)
+    assert_fields_close(f, o.state, TOL64)
+
+
 @pytest.mark.parametrize("mg", [1.0, 1.7, 2.5, 4.0])
 @pytest.mark.parametrize("path", ["fused", "residual"])
 def test_grass_exponent_and_ag_field(sve, mg, path):
