@@ -46,19 +46,25 @@ NX = NY = 2000
 # WRITE_SIZE x 1.0000.  Valid only for the library build it was taken on
 # (hash of the built library) and the automatic tile split; otherwise the
 # bench reports null.  Summary: profiles/k_fused_dune2000_fp64_hbm_traffic.md.
-TRAFFIC = {"src": "ce2e0b93d1cfb374", "rows": 0,
-           "fetch_kib": 68975.1, "write_kib": 125212.8,
-           "bytes_per_launch": 269.47e6}
+TRAFFIC = {"src": "21b20e2b032027c4", "rows": 0,
+           "fetch_kib": 68987.1, "write_kib": 125208.8,
+           "bytes_per_launch": 269.49e6}
 
 # VALU activity of the same kernel, build and workload (rocprofv3 --pmc
 # SQ_INSTS_VALU, SQ_INSTS_VALU_TRANS_F64; wavefront instructions per
 # dispatch, summed over the device).  The chip issues one wave64 VALU
 # instruction per SIMD every 4 cycles (16 for FP64 transcendentals):
 # 256 CUs x 4 SIMDs at 2.4 GHz.  Summary: profiles/k_fused_dune2000_fp64_valu.md.
-VALU = {"src": "ce2e0b93d1cfb374", "rows": 0,
+VALU = {"src": "21b20e2b032027c4", "rows": 0,
         "insts_valu": 41176610, "insts_trans_f64": 1111242}
 SIMDS = 256 * 4
 CLOCK_HZ = 2.4e9
+# Algorithmic FP64 operations per 2D cell-update (estimate: about 110 flops,
+# 3 square roots and 3 divisions per interface solve, two interfaces per
+# cell, and about 30 for the Grass m_g = 3 closure), against the 78.6
+# TFLOP/s FP64 vector peak.
+ALG_FLOPS_PER_CELL = 2 * (110 + 3 + 3) + 30
+FP64_PEAK_TFLOPS = 78.6
 
 
 def kernel_source_hash() -> str:
@@ -144,6 +150,26 @@ def copy_calibration(torch, mib: int, reps: int = 5):
         torch.mul(a, 1.0, out=b)
     torch.cuda.synchronize()
     return {"bytes_read": 8 * n, "bytes_written": 8 * n, "reps": reps}
+
+
+def copy_peak(torch, mib: int = 1024, reps: int = 10) -> float:
+    """Achieved HBM bandwidth of a plain streaming kernel (b = a * 1, float64,
+    `mib` MiB read and written per launch), GB/s, timed with events on
+    torch's stream, where the kernel runs."""
+    n = mib * 1024 * 1024 // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.mul(a, 1.0, out=b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.mul(a, 1.0, out=b)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 16.0 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    return gbs
 
 
 def mpm_leg(args, sve, torch):
@@ -438,15 +464,19 @@ def main():
         out["value"] = cells * args.steps / wall
         out["ms_per_step"] = wall * 1e3 / args.steps
         out["config"].update({"sim_time_s": t, "steps_done": ns})
-        valu = None
+        alg_tflops = ALG_FLOPS_PER_CELL * cells / per_launch_s / 1e12
+        valu = {"algorithmic_flops_per_cell": ALG_FLOPS_PER_CELL,
+                "algorithmic_tflops": alg_tflops,
+                "fp64_peak_tflops": FP64_PEAK_TFLOPS,
+                "fp64_frac": alg_tflops / FP64_PEAK_TFLOPS}
         if VALU["src"] == src and args.path == "fused" and args.rows == VALU["rows"]:
             cycles = (4 * (VALU["insts_valu"] - VALU["insts_trans_f64"])
                       + 16 * VALU["insts_trans_f64"]) / SIMDS
             issue_s = cycles / CLOCK_HZ
-            valu = {"lane_instructions_per_cell": VALU["insts_valu"] * 64 / cells,
-                    "fp64_transcendental_per_cell": VALU["insts_trans_f64"] * 64 / cells,
-                    "issue_us_at_2.4GHz": issue_s * 1e6,
-                    "issue_busy_frac": issue_s / per_launch_s}
+            valu.update({"lane_instructions_per_cell": VALU["insts_valu"] * 64 / cells,
+                         "fp64_transcendental_per_cell": VALU["insts_trans_f64"] * 64 / cells,
+                         "issue_us_at_2.4GHz": issue_s * 1e6,
+                         "issue_busy_frac": issue_s / per_launch_s})
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                            "traffic_unit": "HBM bytes per launch",
@@ -456,6 +486,9 @@ def main():
                            "bytes_per_cell": BYTES_PER_CELL_FP64,
                            "avg_launch_us": per_launch_s * 1e6, "kernel_src": src,
                            "valu": valu}
+        cp = copy_peak(torch)
+        out["roofline"]["measured_copy_GBs"] = cp
+        out["roofline"]["frac_of_measured_copy"] = achieved / cp
         if not ok:
             out["error"] = "non-finite or non-positive depth after the run"
     if args.copy_calib:
