@@ -48,13 +48,13 @@ __device__ __forceinline__ void ens_tile(const EnsMember* __restrict__ mem, cons
                                          int n, double cfl, int TY) {
     const EnsMember& E = mem[t.m];
     Ctrl* ctrl = E.ctrl;
-    if (ctrl->err) return;
-    const StepTime st = step_time(E.M, ctrl, n, cfl, 0.0, 0.0);
-    if (t.tx == 0 && t.ty == 0 && (threadIdx.x & 63) == 0) step_bookkeeping(ctrl, n, st);
     const StateView<double> S = view(E.buf[n & 1], E.pitch);
     const StateView<double> D = view(E.buf[(n + 1) & 1], E.pitch);
     const int j0 = t.ty * TY;
-    fused_tile<double, CL_GRASSM, true>(E.M, S, D, nullptr, ctrl, n, st, t.tx, j0,
+    // the tile checks the member's error flag and does the member's step
+    // bookkeeping (its first tile) after requesting its first rows
+    fused_tile<double, CL_GRASSM, true>(E.M, S, D, nullptr, ctrl, n, cfl, 0.0, 0.0,
+                                        t.tx == 0 && t.ty == 0, t.tx, j0,
                                         min(j0 + TY, E.M.ny));
 }
 

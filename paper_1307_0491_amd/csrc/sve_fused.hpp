@@ -112,6 +112,9 @@ struct Raw {
 
 // Row r of the tile: wrapped or clamped row index and the INFLOW side that
 // replaces (h, hu, hv) of a ghost row (-1 when none).
+// Row r of the tile: wrapped or clamped row index and the INFLOW side that
+// replaces (h, hu, hv) of a ghost row (-1 when none).  (The side index is
+// wave-uniform, so the model's array is read by a scalar load.)
 __device__ __forceinline__ void row_index(const Model& M, int r, int& jj, int& gin) {
     jj = r;
     int g = -1;
@@ -121,6 +124,24 @@ __device__ __forceinline__ void row_index(const Model& M, int r, int& jj, int& g
         if (M.bc_kind[BCN] == BC_PERIODIC) jj = wrap(r, M.ny); else { jj = M.ny - 1; g = BCN; }
     }
     gin = (g >= 0 && M.bc_kind[g] == BC_INFLOW) ? g : -1;
+}
+
+// Column `col` of a lane: wrapped or clamped index and the INFLOW side that
+// replaces (h, hu, hv) of a ghost column (-1 when none).  The model's
+// array is read with constant indices: a lane-dependent index makes the
+// compiler fetch the kernel argument through memory, a round trip before
+// the tile's first loads.
+__device__ __forceinline__ void column_index(const Model& M, int col, int& ci, int& gin) {
+    const int kW = M.bc_kind[BCW], kE = M.bc_kind[BCE];
+    ci = col;
+    gin = -1;
+    if (col < 0) {
+        if (kW == BC_PERIODIC) ci = wrap(col, M.nx);
+        else { ci = 0; if (kW == BC_INFLOW) gin = BCW; }
+    } else if (col >= M.nx) {
+        if (kE == BC_PERIODIC) ci = wrap(col, M.nx);
+        else { ci = M.nx - 1; if (kE == BC_INFLOW) gin = BCE; }
+    }
 }
 
 // Inflow values of the ghost cells a tile can touch and the uniform A_g,
@@ -209,7 +230,8 @@ struct RowCarry {
 template <typename T, int CL, bool SPEEDS>
 __device__ __forceinline__ void fused_tile(const Model& M, const StateView<T>& S,
                                            const StateView<T>& D, const double* __restrict__ Agf,
-                                           Ctrl* ctrl, int n, const StepTime& st, int tx, int j0,
+                                           Ctrl* ctrl, int n, double cfl, double t_end,
+                                           double fixed_dt, bool bookkeep, int tx, int j0,
                                            int jend) {
     const int lane = threadIdx.x & 63;
     const int i0 = tx * FUSED_OWN;
@@ -222,18 +244,13 @@ __device__ __forceinline__ void fused_tile(const Model& M, const StateView<T>& S
     const bool xghost_w = (i0 == 0) && M.bc_kind[BCW] != BC_PERIODIC;
     const bool yghost_n = (jend == M.ny) && M.bc_kind[BCN] != BC_PERIODIC;
     const bool yghost_s = (j0 == 0) && M.bc_kind[BCS] != BC_PERIODIC;
-    const double lx = st.dt / M.dx, ly = st.dt / M.dy;
 
     // column of this lane: wrapped or clamped, and its INFLOW ghost side
-    int ci = col, gx = -1;
-    if (col < 0) {
-        if (M.bc_kind[BCW] == BC_PERIODIC) ci = wrap(col, M.nx); else { ci = 0; gx = BCW; }
-    } else if (col >= M.nx) {
-        if (M.bc_kind[BCE] == BC_PERIODIC) ci = wrap(col, M.nx); else { ci = M.nx - 1; gx = BCE; }
-    }
-    const int gxin = (gx >= 0 && M.bc_kind[gx] == BC_INFLOW) ? gx : -1;
+    int ci, gxin;
+    column_index(M, col, ci, gxin);
     const Ghosts G = make_ghosts(M, gxin);
     double sx = 0.0, sy = 0.0;
+    double dt = 0.0, lx = 0.0, ly = 0.0;            // set once the step's time is known
 
     // Row r with the row loaded for it in `cur`.  DO_X: x-interfaces of row
     // r; DO_UPD: update of row r-1 (RING: that row is the ring row, not
@@ -267,7 +284,7 @@ __device__ __forceinline__ void fused_tile(const Model& M, const StateView<T>& S
             double hun = c.hu - lx * c.dXm - ly * (Y.Fht - c.Yt);
             double hvn = c.hv - lx * c.dXt - ly * (Y.FhuL - c.YR);
             double zn = c.z - lx * c.dXz - ly * (Y.Fz - c.Yz);
-            if (M.momentum_friction) apply_friction(M, st.dt, hn, hun, hvn);
+            if (M.momentum_friction) apply_friction(M, dt, hn, hun, hvn);
             if (!ring.value && owned_lane) {
                 const unsigned e = check_state(hn, hun, hvn, zn) | c.eX | c.eY | eY;
                 if (e) record_error(ctrl, e, n);
@@ -331,16 +348,26 @@ __device__ __forceinline__ void fused_tile(const Model& M, const StateView<T>& S
     using Y_ = std::true_type;
     using N_ = std::false_type;
 
+    // The first three rows are requested before the control block is read,
+    // so their loads overlap the scalar loads of the error flag and the
+    // step's time (the loads are in bounds whatever the flag says).
+    const Raw w = load_row(M, S, Agf, G, ci, gxin, j0 - 1);
+    Raw cur = load_row(M, S, Agf, G, ci, gxin, j0);
+    Raw nxt = load_row(M, S, Agf, G, ci, gxin, j0 + 1);
+    if (ctrl->err) return;                           // a previous step failed
+    const StepTime st = step_time(M, ctrl, n, cfl, t_end, fixed_dt);
+    if (bookkeep && lane == 0) step_bookkeeping(ctrl, n, st);
+    dt = st.dt;
+    lx = dt / M.dx;
+    ly = dt / M.dy;
+
     // row j0-1: projection only
     RowCarry c{};
     {
-        const Raw w = load_row(M, S, Agf, G, ci, gxin, j0 - 1);
         const Cell P = project<CL>(M, w.h, w.hu, w.hv, w.z, w.ag);
         c.h = P.h; c.tau = P.tau; c.u = P.u; c.v = P.v; c.Pi = P.Pi; c.z = P.z; c.qy = P.qy;
         c.by2 = P.by2; c.aK = P.aK; c.inv = P.inv_aK; c.hu = P.hu; c.hv = P.hv; c.ag = w.ag;
     }
-    Raw cur = load_row(M, S, Agf, G, ci, gxin, j0);
-    Raw nxt = load_row(M, S, Agf, G, ci, gxin, j0 + 1);
     row(c, cur, j0, Y_{}, N_{}, N_{}, N_{});                       // row j0: fluxes only
     cur = nxt;
     if (j0 + 1 < j_ring) {
@@ -376,14 +403,12 @@ template <typename T, int CL, bool SPEEDS>
 __global__ void __launch_bounds__(64, FUSED_WAVES_PER_SIMD)
 k_fused(Model M, StateView<T> S, StateView<T> D, const double* __restrict__ Agf, Ctrl* ctrl,
         int n, double cfl, double t_end, double fixed_dt, int tiles_y) {
-    if (ctrl->err) return;
-    const StepTime st = step_time(M, ctrl, n, cfl, t_end, fixed_dt);
-    if (blockIdx.x == 0 && threadIdx.x == 0) step_bookkeeping(ctrl, n, st);
     const int tiles_x = (M.nx + FUSED_OWN - 1) / FUSED_OWN;
     const int t = xcd_tile(blockIdx.x, tiles_x * tiles_y);
     int j0, jend;
     tile_rows(M.ny, tiles_y, t / tiles_x, j0, jend);
-    fused_tile<T, CL, SPEEDS>(M, S, D, Agf, ctrl, n, st, t % tiles_x, j0, jend);
+    fused_tile<T, CL, SPEEDS>(M, S, D, Agf, ctrl, n, cfl, t_end, fixed_dt, blockIdx.x == 0,
+                              t % tiles_x, j0, jend);
 }
 
 // tiles_y: number of row tiles (fused_tiles_y), 1 <= tiles_y <= ny.

@@ -43,13 +43,8 @@ __device__ __forceinline__ void resid_tile(const Model& M, const StateView<T>& S
     const double rdx = 1.0 / M.dx, rdy = 1.0 / M.dy;
     const int flux_step = INIT ? n : n + 1;          // step whose fluxes are solved here
 
-    int ci = col, gx = -1;
-    if (col < 0) {
-        if (M.bc_kind[BCW] == BC_PERIODIC) ci = wrap(col, M.nx); else { ci = 0; gx = BCW; }
-    } else if (col >= M.nx) {
-        if (M.bc_kind[BCE] == BC_PERIODIC) ci = wrap(col, M.nx); else { ci = M.nx - 1; gx = BCE; }
-    }
-    const int gxin = (gx >= 0 && M.bc_kind[gx] == BC_INFLOW) ? gx : -1;
+    int ci, gxin;
+    column_index(M, col, ci, gxin);
     const Ghosts G = make_ghosts(M, gxin);
 
     // Row r on this lane's column: U^n, R^n and A_g as loaded (load), then
