@@ -46,17 +46,17 @@ NX = NY = 2000
 # WRITE_SIZE x 1.0000.  Valid only for the library build it was taken on
 # (hash of the built library) and the automatic tile split; otherwise the
 # bench reports null.  Summary: profiles/k_fused_dune2000_fp64_hbm_traffic.md.
-TRAFFIC = {"src": "21b20e2b032027c4", "rows": 0,
-           "fetch_kib": 68987.1, "write_kib": 125208.8,
-           "bytes_per_launch": 269.49e6}
+TRAFFIC = {"src": "e6405ded39e96bbc", "rows": 0,
+           "fetch_kib": 68979.9, "write_kib": 125208.9,
+           "bytes_per_launch": 269.48e6}
 
 # VALU activity of the same kernel, build and workload (rocprofv3 --pmc
 # SQ_INSTS_VALU, SQ_INSTS_VALU_TRANS_F64; wavefront instructions per
 # dispatch, summed over the device).  The chip issues one wave64 VALU
 # instruction per SIMD every 4 cycles (16 for FP64 transcendentals):
 # 256 CUs x 4 SIMDs at 2.4 GHz.  Summary: profiles/k_fused_dune2000_fp64_valu.md.
-VALU = {"src": "21b20e2b032027c4", "rows": 0,
-        "insts_valu": 41176610, "insts_trans_f64": 1111242}
+VALU = {"src": "e6405ded39e96bbc", "rows": 0,
+        "insts_valu": 41170596, "insts_trans_f64": 1111242}
 SIMDS = 256 * 4
 CLOCK_HZ = 2.4e9
 # Algorithmic FP64 operations per 2D cell-update (estimate: about 110 flops,
