@@ -63,13 +63,13 @@ int sve_ens_get(sve_ens *ens, int m, double *h, double *hu, double *hv, double *
                 double *t, long long *nsteps);
 
 /*
- * Time nprobe steps for each tile height in {8, 16, 32, 48, 64} and both modes
+ * Time nprobe steps for each tile height in {8, 16, 32, 48, 64, 96, 128} and both modes
  * (member states are saved before and restored after) and keep the fastest;
  * *rows and *mode (may be NULL) receive the choice.
  */
 int sve_ens_autotune(sve_ens *ens, int nprobe, double cfl, int *rows, int *mode);
 
-/* Set the schedule directly (rows in {8, 16, 32, 48, 64}, mode SVE_ENS_*). */
+/* Set the schedule directly (rows in {8, 16, 32, 48, 64, 96, 128}, mode SVE_ENS_*). */
 int sve_ens_set_schedule(sve_ens *ens, int rows, int mode);
 
 /* Milliseconds between HIP events around the last step call's launches. */

@@ -416,7 +416,8 @@ int sve_ens_get(sve_ens* e, int m, double* h, double* hu, double* hv, double* zb
 }
 
 int sve_ens_set_schedule(sve_ens* e, int rows, int mode) {
-    if (!e || (rows != 8 && rows != 16 && rows != 32 && rows != 48 && rows != 64))
+    if (!e || (rows != 8 && rows != 16 && rows != 32 && rows != 48 && rows != 64 && rows != 96 &&
+               rows != 128))
         return SVE_ERR_ARG;
     if (mode != SVE_ENS_QUEUE && mode != SVE_ENS_GRID) return SVE_ERR_ARG;
     e->rows = rows;
@@ -451,7 +452,7 @@ int sve_ens_autotune(sve_ens* e, int nprobe, double cfl, int* rows, int* mode) {
         e->nsteps = n_saved;
         return ok;
     };
-    const int cand_rows[5] = {8, 16, 32, 48, 64};
+    const int cand_rows[7] = {8, 16, 32, 48, 64, 96, 128};
     double best = 1e300;
     int best_rows = e->rows, best_mode = e->mode;
     for (int md = 0; md < 2; ++md) {

@@ -38,7 +38,7 @@ def oracle_run(m, nsteps):
     return o
 
 
-@pytest.mark.parametrize("mode,rows", [(0, 16), (1, 16), (0, 8), (1, 32)])
+@pytest.mark.parametrize("mode,rows", [(0, 16), (1, 16), (0, 8), (1, 32), (0, 128), (1, 96)])
 def test_ensemble_members_match_oracle(sve, mode, rows):
     from paper_1307_0491_amd.ensemble import Ensemble
     ms = members()
