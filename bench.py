@@ -43,10 +43,10 @@ NX = NY = 2000
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each
 # scaled by the ratio of known bytes to the same counter on a plain
 # streaming kernel (1 GiB read, 1 GiB written): FETCH_SIZE x 2.0000,
-# WRITE_SIZE x 1.0000.  Valid only for the library build it was taken on
-# (hash of the built library) and the automatic tile split; otherwise the
-# bench reports null.  Summary: profiles/k_fused_dune2000_fp64_hbm_traffic.md.
-TRAFFIC = {"src": "e6405ded39e96bbc", "rows": 0,
+# WRITE_SIZE x 1.0000.  Valid only for the kernel sources it was taken on
+# (kernel_source_hash) and the automatic tile split; otherwise the bench
+# reports null.  Summary: profiles/k_fused_dune2000_fp64_hbm_traffic.md.
+TRAFFIC = {"src": "7f6eb8c4eee3ffa2", "rows": 0,
            "fetch_kib": 68979.9, "write_kib": 125208.9,
            "bytes_per_launch": 269.48e6}
 
@@ -55,7 +55,7 @@ TRAFFIC = {"src": "e6405ded39e96bbc", "rows": 0,
 # dispatch, summed over the device).  The chip issues one wave64 VALU
 # instruction per SIMD every 4 cycles (16 for FP64 transcendentals):
 # 256 CUs x 4 SIMDs at 2.4 GHz.  Summary: profiles/k_fused_dune2000_fp64_valu.md.
-VALU = {"src": "e6405ded39e96bbc", "rows": 0,
+VALU = {"src": "7f6eb8c4eee3ffa2", "rows": 0,
         "insts_valu": 41170596, "insts_trans_f64": 1111242}
 SIMDS = 256 * 4
 CLOCK_HZ = 2.4e9
@@ -67,13 +67,22 @@ ALG_FLOPS_PER_CELL = 2 * (110 + 3 + 3) + 30
 FP64_PEAK_TFLOPS = 78.6
 
 
+# What the step kernel's code and launch are built from: its sources, the
+# host code that sizes its grid, and the build flags.
+KERNEL_SOURCES = ("paper_1307_0491_amd/csrc/sve_api.hip", "paper_1307_0491_amd/csrc/sve_fused.hpp",
+                  "paper_1307_0491_amd/csrc/sve_kernels.hpp",
+                  "paper_1307_0491_amd/csrc/sve_device.hpp",
+                  "paper_1307_0491_amd/csrc/sve_context.hpp", "include/sve.h",
+                  "paper_1307_0491_amd/build.py")
+
+
 def kernel_source_hash() -> str:
-    """Hash of the built HIP library (its code objects hold the kernels;
-    rebuilding unchanged sources gives the same file)."""
-    import paper_1307_0491_amd._lib as L
+    """Hash of the files the step kernel is built and launched from (any
+    change to them, comments included, invalidates the recorded counters)."""
     h = hashlib.sha256()
-    with open(L.LIB_PATH, "rb") as f:
-        h.update(f.read())
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(rel.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
 
 
