@@ -79,6 +79,8 @@ KERNEL_SOURCES = ("paper_1307_0491_amd/csrc/sve_api.hip", "paper_1307_0491_amd/c
 def kernel_source_hash() -> str:
     """Hash of the files the step kernel is built and launched from (any
     change to them, comments included, invalidates the recorded counters)."""
+    if os.environ.get("SVE_LIBRARY"):
+        return "external"                # a library not built from these sources
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
         with open(os.path.join(ROOT, rel), "rb") as f:
