@@ -226,7 +226,9 @@ struct RowCarry {
 
 // One tile of one step, run by one wavefront: tile tx owns columns
 // [61 tx, 61 tx + 61) (clipped to the grid) and rows [j0, jend), jend > j0.
-// tx, j0, jend and `st` must be wave-uniform.
+// The step's dt follows from the control block (cfl, t_end, fixed_dt as for
+// step_time); exactly one tile of the grid passes bookkeep = true and
+// records the step.  All arguments must be wave-uniform.
 template <typename T, int CL, bool SPEEDS>
 __device__ __forceinline__ void fused_tile(const Model& M, const StateView<T>& S,
                                            const StateView<T>& D, const double* __restrict__ Agf,
