@@ -185,9 +185,14 @@ struct Model {
 
 // Control block in device memory.  Wave-speed maxima and times are
 // triple-buffered by step index: step n reads slot n%3, accumulates the
-// maxima of step n+1 into slot (n+1)%3 and clears slot (n+2)%3.
+// maxima of step n+1 into slot (n+1)%3 and clears slot (n+2)%3.  Each
+// slot holds SPEED_PARTS partial maxima on separate 128-byte lines: the
+// wavefronts of a launch post to part (workgroup id mod SPEED_PARTS), so the
+// atomics of some 2000 wavefronts finishing together do not all queue on
+// one address; readers take the maximum over the parts.
+constexpr int SPEED_PARTS = 8;
 struct Ctrl {
-    unsigned long long smax[3][2];  // bit patterns of max speeds (x, y), >= 0
+    unsigned long long smax[3][SPEED_PARTS][16];  // bit patterns of max speeds (x, y) in [0], [1]
     double t[3];
     double dt_last;
     unsigned err;
@@ -539,6 +544,34 @@ __device__ __forceinline__ unsigned long long double_as_u64(double d) {
 }
 
 // Wavefront maximum of non-negative doubles (64 lanes).
+// Post non-negative maxima (x, y) of a wavefront or workgroup to part
+// `part` of slot `slot` (64-bit atomic max of the bit patterns, which order
+// like the values).
+__device__ __forceinline__ void post_speeds(Ctrl* ctrl, int slot, int part, double sx,
+                                            double sy) {
+    unsigned long long* p = ctrl->smax[slot][part % SPEED_PARTS];
+    if (sx > 0.0) atomicMax(&p[0], double_as_u64(sx));
+    if (sy > 0.0) atomicMax(&p[1], double_as_u64(sy));
+}
+
+// Maximum over the parts of slot `slot`, direction `dir` (0: x, 1: y).
+__device__ __forceinline__ double speed_max(const Ctrl* ctrl, int slot, int dir) {
+    unsigned long long m = 0ull;
+    for (int k = 0; k < SPEED_PARTS; ++k) {
+        const unsigned long long v = ctrl->smax[slot][k][dir];
+        m = v > m ? v : m;
+    }
+    return u64_as_double(m);
+}
+
+// Clear every part of slot `slot` (one thread).
+__device__ __forceinline__ void clear_speeds(Ctrl* ctrl, int slot) {
+    for (int k = 0; k < SPEED_PARTS; ++k) {
+        ctrl->smax[slot][k][0] = 0ull;
+        ctrl->smax[slot][k][1] = 0ull;
+    }
+}
+
 __device__ __forceinline__ double wave_max(double v) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
     return v;
@@ -558,12 +591,12 @@ __device__ __forceinline__ StepTime step_time(const Model& M, const Ctrl* ctrl, 
         st.tnew = st.t + fixed_dt;
         return st;
     }
-    const double Sx = u64_as_double(ctrl->smax[n % 3][0]);
+    const double Sx = speed_max(ctrl, n % 3, 0);
     double dt;
     if (M.dim == 1) {
         dt = cfl * M.dx / Sx;
     } else {
-        const double Sy = u64_as_double(ctrl->smax[n % 3][1]);
+        const double Sy = speed_max(ctrl, n % 3, 1);
         dt = cfl / (Sx / M.dx + Sy / M.dy);
     }
     double tnew = st.t + dt;

@@ -393,8 +393,7 @@ __device__ __forceinline__ void fused_tile(const Model& M, const StateView<T>& S
         sx = wave_max(sx);
         sy = wave_max(sy);
         if (lane == 0) {
-            if (sx > 0.0) atomicMax(&ctrl->smax[(n + 1) % 3][0], double_as_u64(sx));
-            if (sy > 0.0) atomicMax(&ctrl->smax[(n + 1) % 3][1], double_as_u64(sy));
+            post_speeds(ctrl, (n + 1) % 3, blockIdx.x, sx, sy);
         }
     }
 }

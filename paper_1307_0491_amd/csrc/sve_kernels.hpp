@@ -68,8 +68,7 @@ k_speeds(Model M, StateView<T> S, const double* __restrict__ Agf, Ctrl* ctrl, in
     const double bx = block_max<SPEED_BLOCK>(sx, sh[0]);
     const double by = block_max<SPEED_BLOCK>(sy, sh[1]);
     if (threadIdx.x == 0) {
-        if (bx > 0.0) atomicMax(&ctrl->smax[slot][0], double_as_u64(bx));
-        if (by > 0.0) atomicMax(&ctrl->smax[slot][1], double_as_u64(by));
+        post_speeds(ctrl, slot, blockIdx.x, bx, by);
     }
 }
 
@@ -78,8 +77,7 @@ k_speeds(Model M, StateView<T> S, const double* __restrict__ Agf, Ctrl* ctrl, in
 __device__ __forceinline__ void step_bookkeeping(Ctrl* ctrl, int n, const StepTime& st) {
     ctrl->t[(n + 1) % 3] = st.tnew;
     ctrl->dt_last = st.dt;
-    ctrl->smax[(n + 2) % 3][0] = 0ull;
-    ctrl->smax[(n + 2) % 3][1] = 0ull;
+    clear_speeds(ctrl, (n + 2) % 3);
 }
 
 template <typename T>
@@ -186,8 +184,7 @@ __global__ void k_store_state(Model M, StateView<T> S, double* h, double* hu, do
 static __global__ void k_reset_ctrl(Ctrl* ctrl, double t0) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         for (int s = 0; s < 3; ++s) {
-            ctrl->smax[s][0] = 0ull;
-            ctrl->smax[s][1] = 0ull;
+            clear_speeds(ctrl, s);
             ctrl->t[s] = t0;
         }
         ctrl->dt_last = 0.0;
@@ -197,10 +194,7 @@ static __global__ void k_reset_ctrl(Ctrl* ctrl, double t0) {
 }
 
 static __global__ void k_clear_slot(Ctrl* ctrl, int slot) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        ctrl->smax[slot][0] = 0ull;
-        ctrl->smax[slot][1] = 0ull;
-    }
+    if (threadIdx.x == 0 && blockIdx.x == 0) clear_speeds(ctrl, slot);
 }
 
 template <typename T>

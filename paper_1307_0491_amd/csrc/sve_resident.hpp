@@ -204,12 +204,8 @@ k_resident_1d(Model M, StateView<T> S, StateView<T> D, const double* __restrict_
         }
         ctrl->t[nend % 3] = t;
         ctrl->dt_last = dt_last;
-        ctrl->smax[nend % 3][0] = cfl_mode ? double_as_u64(S_cur) : 0ull;
-        ctrl->smax[nend % 3][1] = 0ull;
-        for (int k = 1; k < 3; ++k) {
-            ctrl->smax[(nend + k) % 3][0] = 0ull;
-            ctrl->smax[(nend + k) % 3][1] = 0ull;
-        }
+        for (int k = 0; k < 3; ++k) clear_speeds(ctrl, k);
+        ctrl->smax[nend % 3][0][0] = cfl_mode ? double_as_u64(S_cur) : 0ull;
     }
 }
 

@@ -178,8 +178,7 @@ __device__ __forceinline__ void resid_tile(const Model& M, const StateView<T>& S
     sx = wave_max(sx);
     sy = wave_max(sy);
     if (lane == 0) {
-        if (sx > 0.0) atomicMax(&ctrl->smax[slot][0], double_as_u64(sx));
-        if (sy > 0.0) atomicMax(&ctrl->smax[slot][1], double_as_u64(sy));
+        post_speeds(ctrl, slot, blockIdx.x, sx, sy);
     }
 }
 
@@ -201,8 +200,7 @@ k_resid(Model M, StateView<T> S, StateView<double> RS, StateView<T> D, StateView
         slot = (n + 1) % 3;
     } else if (blockIdx.x == 0 && threadIdx.x == 0) {
         // the first step kernel accumulates into slot (n+1)%3
-        ctrl->smax[(n + 1) % 3][0] = 0ull;
-        ctrl->smax[(n + 1) % 3][1] = 0ull;
+        clear_speeds(ctrl, (n + 1) % 3);
     }
     const int tiles_x = (M.nx + FUSED_OWN - 1) / FUSED_OWN;
     const int t = xcd_tile(blockIdx.x, tiles_x * tiles_y);
