@@ -187,9 +187,12 @@ struct Model {
 // triple-buffered by step index: step n reads slot n%3, accumulates the
 // maxima of step n+1 into slot (n+1)%3 and clears slot (n+2)%3.  Each
 // slot holds SPEED_PARTS partial maxima on separate 128-byte lines: the
-// wavefronts of a launch post to part (workgroup id mod SPEED_PARTS), so the
+// wavefronts of a launch post to part (workgroup id mod SPEED_PARTS, which
+// is also the XCD that round-robin dispatch gives the workgroup), so the
 // atomics of some 2000 wavefronts finishing together do not all queue on
-// one address; readers take the maximum over the parts.
+// one address; readers take the maximum over the parts.  (Eight parts
+// measured faster than 16 or 32, and faster than reading a part before
+// posting to skip atomics that cannot raise it.)
 constexpr int SPEED_PARTS = 8;
 struct Ctrl {
     unsigned long long smax[3][SPEED_PARTS][16];  // bit patterns of max speeds (x, y) in [0], [1]
