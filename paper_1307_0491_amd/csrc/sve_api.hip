@@ -144,6 +144,7 @@ void launch_speeds(sve_ctx* c, int buf, int slot) {
     auto kern = cl == CL_GRASS3 ? k_speeds<T, CL_GRASS3>
               : cl == CL_GRASS1 ? k_speeds<T, CL_GRASS1>
               : cl == CL_GRASSM ? k_speeds<T, CL_GRASSM>
+              : cl == CL_MPM    ? k_speeds<T, CL_MPM>
                                 : k_speeds<T, CL_THRESH>;
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(SPEED_BLOCK), 0, c->stream, M,
                        view_of<T>(c, buf), (const double*)c->Ag, c->ctrl, slot);
@@ -159,6 +160,7 @@ void launch_update(sve_ctx* c, int src, int dst, int n, double cfl, double t_end
     auto kern = cl == CL_GRASS3 ? k_update<T, CL_GRASS3>
               : cl == CL_GRASS1 ? k_update<T, CL_GRASS1>
               : cl == CL_GRASSM ? k_update<T, CL_GRASSM>
+              : cl == CL_MPM    ? k_update<T, CL_MPM>
                                 : k_update<T, CL_THRESH>;
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(UPDATE_BLOCK), 0, c->stream, M,
                        view_of<T>(c, src), view_of<T>(c, dst), (const double*)c->Ag, c->ctrl,

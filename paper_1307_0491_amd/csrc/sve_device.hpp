@@ -267,10 +267,13 @@ __device__ __forceinline__ void threshold_law(int law, double theta, double tc,
 }
 
 // Closure families compiled as separate kernel instantiations, so that the
-// common Grass m_g = 3 path carries no pow/exp/cbrt code (register pressure).
-enum { CL_GRASS3 = 0, CL_GRASS1 = 1, CL_GRASSM = 2, CL_THRESH = 3 };
+// common Grass m_g = 3 path carries no pow/exp/cbrt code and the
+// Meyer-Peter & Mueller kernels none of the other threshold laws (register
+// pressure); CL_THRESH covers the other four threshold laws.
+enum { CL_GRASS3 = 0, CL_GRASS1 = 1, CL_GRASSM = 2, CL_THRESH = 3, CL_MPM = 4 };
 
 inline int closure_class(const Model& M) {
+    if (M.law == LAW_MPM) return CL_MPM;
     if (M.law != LAW_GRASS) return CL_THRESH;
     if (M.mg_is3) return CL_GRASS3;
     if (M.mg_is1) return CL_GRASS1;
@@ -290,7 +293,7 @@ __device__ __forceinline__ void closure(const Model& M, double h, double u,
                                         double& qy, double& bx, double& by) {
     const double uu = u * u, vv = v * v;
     const double w = uu + vv;
-    if (CL != CL_THRESH) {
+    if (CL != CL_THRESH && CL != CL_MPM) {
         if (CL == CL_GRASS3) {
             qx = Ag * w * u;
             qy = Ag * w * v;
@@ -318,9 +321,9 @@ __device__ __forceinline__ void closure(const Model& M, double h, double u,
         }
         return;
     }
-    const double c = (M.friction == FRIC_DARCY) ? M.c_const : M.c_const / cbrt(h);
+    const double c = (M.friction == FRIC_DARCY) ? M.c_const : M.c_const * rcbrt(h);
     double F, dF;
-    threshold_law(M.law, c * w, M.tau_cr, F, dF);
+    threshold_law(CL == CL_MPM ? LAW_MPM : M.law, c * w, M.tau_cr, F, dF);
     if (w > 0.0) {
         const double im = frsq(w);                          // 1 / |U|
         const double Q = M.K * F;

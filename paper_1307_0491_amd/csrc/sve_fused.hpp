@@ -424,6 +424,7 @@ void launch_fused_rows(const Model& M, StateView<T> S, StateView<T> D, const dou
     auto kern = cl == CL_GRASS3 ? (sp ? k_fused<T, CL_GRASS3, true> : k_fused<T, CL_GRASS3, false>)
               : cl == CL_GRASS1 ? (sp ? k_fused<T, CL_GRASS1, true> : k_fused<T, CL_GRASS1, false>)
               : cl == CL_GRASSM ? (sp ? k_fused<T, CL_GRASSM, true> : k_fused<T, CL_GRASSM, false>)
+              : cl == CL_MPM    ? (sp ? k_fused<T, CL_MPM, true> : k_fused<T, CL_MPM, false>)
                                 : (sp ? k_fused<T, CL_THRESH, true> : k_fused<T, CL_THRESH, false>);
     hipLaunchKernelGGL(kern, grid, dim3(64), 0, stream, M, S, D, Ag, ctrl, n, cfl, t_end,
                        fixed_dt, tiles_y);

@@ -235,6 +235,7 @@ void launch_resident(sve_ctx* c, int n, double cfl, double t_end, double fixed_d
     auto kern = cl == CL_GRASS3 ? k_resident_1d<T, CL_GRASS3>
               : cl == CL_GRASS1 ? k_resident_1d<T, CL_GRASS1>
               : cl == CL_GRASSM ? k_resident_1d<T, CL_GRASSM>
+              : cl == CL_MPM    ? k_resident_1d<T, CL_MPM>
                                 : k_resident_1d<T, CL_THRESH>;
     hipLaunchKernelGGL(kern, dim3(1), dim3(RES_BLOCK), lds, c->stream,
                        c->M, S, D, (const double*)c->Ag, c->ctrl, (int)c->nsteps, n, cfl, t_end,

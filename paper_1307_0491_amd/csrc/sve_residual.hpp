@@ -218,6 +218,7 @@ void launch_resid(const Model& M, StateView<T> S, StateView<double> RS, StateVie
     auto kern = cl == CL_GRASS3 ? k_resid<T, CL_GRASS3, INIT>
               : cl == CL_GRASS1 ? k_resid<T, CL_GRASS1, INIT>
               : cl == CL_GRASSM ? k_resid<T, CL_GRASSM, INIT>
+              : cl == CL_MPM    ? k_resid<T, CL_MPM, INIT>
                                 : k_resid<T, CL_THRESH, INIT>;
     hipLaunchKernelGGL(kern, dim3(tiles_x * tiles_y), dim3(64), 0, stream, M, S, RS, D, RD, Ag,
                        ctrl, n, cfl, t_end, tiles_y);
