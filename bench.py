@@ -46,7 +46,7 @@ NX = NY = 2000
 # WRITE_SIZE x 1.0000.  Valid only for the kernel sources it was taken on
 # (kernel_source_hash) and the automatic tile split; otherwise the bench
 # reports null.  Summary: profiles/k_fused_dune2000_fp64_hbm_traffic.md.
-TRAFFIC = {"src": "ae5514e2881c5fde", "rows": 0,
+TRAFFIC = {"src": "34586b0effa01e52", "rows": 0,
            "fetch_kib": 68969.0, "write_kib": 125208.0,
            "bytes_per_launch": 269.45e6}
 
@@ -55,7 +55,7 @@ TRAFFIC = {"src": "ae5514e2881c5fde", "rows": 0,
 # dispatch, summed over the device).  The chip issues one wave64 VALU
 # instruction per SIMD every 4 cycles (16 for FP64 transcendentals):
 # 256 CUs x 4 SIMDs at 2.4 GHz.  Summary: profiles/k_fused_dune2000_fp64_valu.md.
-VALU = {"src": "ae5514e2881c5fde", "rows": 0,
+VALU = {"src": "34586b0effa01e52", "rows": 0,
         "insts_valu": 41252436, "insts_trans_f64": 1111242}
 SIMDS = 256 * 4
 CLOCK_HZ = 2.4e9
