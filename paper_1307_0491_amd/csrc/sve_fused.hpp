@@ -201,6 +201,34 @@ __device__ __forceinline__ Raw load_row(const Model& M, const StateView<T>& S,
     return w;
 }
 
+// Row r, 0 <= r < ny, of the tile: no ghost row to apply, and the column's
+// INFLOW values are not applied yet (inflow_column does that).
+template <typename T>
+__device__ __forceinline__ Raw load_row_inner(const Model& M, const StateView<T>& S,
+                                              const double* __restrict__ Agf, const Ghosts& G,
+                                              int ci, int r) {
+    const long long k = (long long)r * M.nx + ci;
+    Raw w;
+    w.h = (double)S.h[k];
+    w.hu = (double)S.hu[k];
+    w.hv = (double)S.hv[k];
+    w.z = (double)S.z[k];
+    w.ag = Agf ? Agf[k] : G.ag;
+    return w;
+}
+
+// The column's INFLOW values for a row from load_row_inner, applied only in
+// tiles that have such a column (xin, wave-uniform).  The empty asm
+// statement keeps the test a branch, so the other tiles skip the selects
+// instead of executing them on every row.  Called once the row's loads are
+// needed anyway: selecting right after the loads would wait for them.
+__device__ __forceinline__ void inflow_column(const Ghosts& G, int gxin, bool xin, Raw& w) {
+    if (xin) {
+        __asm__ volatile("");
+        apply_inflow(G, gxin, -1, w.h, w.hu, w.hv);
+    }
+}
+
 // Side of a ghost cell next to a cell with side `c` (FREE: the same cell;
 // INFLOW: the Dirichlet (h, hu, hv) with the cell's bed and A_g).
 template <int CL>
@@ -251,6 +279,10 @@ __device__ __forceinline__ void fused_tile(const Model& M, const StateView<T>& S
     int ci, gxin;
     column_index(M, col, ci, gxin);
     const Ghosts G = make_ghosts(M, gxin);
+    // some lane of the tile is an INFLOW ghost column (lane 63 holds the
+    // tile's last column, i0 + 62)
+    const bool xin = (i0 == 0 && M.bc_kind[BCW] == BC_INFLOW) ||
+                     (i0 + 62 >= M.nx && M.bc_kind[BCE] == BC_INFLOW);
     double sx = 0.0, sy = 0.0;
     double dt = 0.0, lx = 0.0, ly = 0.0;            // set once the step's time is known
 
@@ -376,9 +408,15 @@ __device__ __forceinline__ void fused_tile(const Model& M, const StateView<T>& S
         nxt = load_row(M, S, Agf, G, ci, gxin, j0 + 2);
         row(c, cur, j0 + 1, Y_{}, Y_{}, N_{}, Y_{});               // update of row j0
         cur = nxt;
-        for (int r = j0 + 2; r < j_ring; ++r) {                   // owned rows j0+1 .. jend-2
-            nxt = load_row(M, S, Agf, G, ci, gxin, r + 1);
+        for (int r = j0 + 2; r < j_ring - 1; ++r) {               // owned rows j0+1 .. jend-3
+            nxt = load_row_inner(M, S, Agf, G, ci, r + 1);           // r + 1 < jend <= ny
             row(c, cur, r, Y_{}, Y_{}, N_{}, N_{});
+            cur = nxt;
+            inflow_column(G, gxin, xin, cur);
+        }
+        if (j0 + 2 < j_ring) {                                     // row jend may be a ghost row
+            nxt = load_row(M, S, Agf, G, ci, gxin, j_ring);
+            row(c, cur, j_ring - 1, Y_{}, Y_{}, N_{}, N_{});       // update of row jend-2
             cur = nxt;
         }
         nxt = load_row(M, S, Agf, G, ci, gxin, j_ring + 1);
