@@ -49,7 +49,7 @@ struct Lam {
 __device__ __forceinline__ SideAdj prev_lane(const SideAdj& s) {
     return SideAdj{dpp<DPP_PREV>(s.h),  dpp<DPP_PREV>(s.tau), dpp<DPP_PREV>(s.un),
                    dpp<DPP_PREV>(s.ut), dpp<DPP_PREV>(s.Pi),  dpp<DPP_PREV>(s.z),
-                   dpp<DPP_PREV>(s.q),  dpp<DPP_PREV>(s.b2),  dpp<DPP_PREV>(s.aK)};
+                   dpp<DPP_PREV>(s.q),  dpp<DPP_PREV>(s.b2)};
 }
 
 // lambda^n = (dU^{n+1}/dU^n)^T lambda^{n+1}; gAg += (dU^{n+1}/dA_g)^T lambda^{n+1}
@@ -98,7 +98,7 @@ k_adjoint_march(Model M, StateView<double> U, const double* __restrict__ Agf,
     Side Sp;
     double hp, hup, hvp, agp;
     Lam lp;
-    CellAdj acc{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    CellAdj acc{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     {
         Cell P;
         load(j0 - 1, P, lp, agp);
@@ -110,7 +110,7 @@ k_adjoint_march(Model M, StateView<double> U, const double* __restrict__ Agf,
         Lam l;
         double ag;
         load(r, P, l, ag);
-        CellAdj an{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        CellAdj an{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
         {                                            // y-interface (r-1 | r)
             const Flux Fb{ly * (l.h - lp.h), -ly * lp.hv, ly * l.hv, ly * (l.hu - lp.hu),
                           ly * (l.z - lp.z)};

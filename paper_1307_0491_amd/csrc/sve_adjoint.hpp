@@ -17,12 +17,12 @@ namespace sve {
 // Adjoints of the projected quantities of one side of an interface (normal
 // frame, as in Side).
 struct SideAdj {
-    double h, tau, un, ut, Pi, z, q, b2, aK;
+    double h, tau, un, ut, Pi, z, q, b2;
 };
 
 // Adjoints of the projected quantities of a cell (x/y frame, as in Cell).
 struct CellAdj {
-    double h, tau, u, v, Pi, z, qx, qy, bx2, by2, aK;
+    double h, tau, u, v, Pi, z, qx, qy, bx2, by2;
 };
 
 // a += x where c holds.  Written as a select so that conditional
@@ -32,11 +32,11 @@ __device__ __forceinline__ void add_if(double& a, bool c, double x) { a += c ? x
 
 __device__ __forceinline__ void add_x(CellAdj& c, const SideAdj& s) {
     c.h += s.h; c.tau += s.tau; c.u += s.un; c.v += s.ut; c.Pi += s.Pi; c.z += s.z;
-    c.qx += s.q; c.bx2 += s.b2; c.aK += s.aK;
+    c.qx += s.q; c.bx2 += s.b2;
 }
 __device__ __forceinline__ void add_y(CellAdj& c, const SideAdj& s) {
     c.h += s.h; c.tau += s.tau; c.v += s.un; c.u += s.ut; c.Pi += s.Pi; c.z += s.z;
-    c.qy += s.q; c.by2 += s.b2; c.aK += s.aK;
+    c.qy += s.q; c.by2 += s.b2;
 }
 
 // Reverse of iface_flux: given the adjoints of (F_h, F_hu^L, F_hu^R, F_ht,
@@ -50,20 +50,19 @@ __device__ __forceinline__ void iface_vjp(const Side& L, const Side& R, double g
     const bool hmaxL = L.h >= R.h;
     const double hmax = dmax(L.h, R.h);
     const double af2 = g * (hmax * hmax * hmax);
-    const bool afL = L.aK >= R.aK;
+    // 1 / a_f, a_f = max(h sqrt(g h)): the cell with the larger h (hmaxL)
     const double inv_af = dmin(L.inv_aK, R.inv_aK);
-    const double a_f = dmax(L.aK, R.aK);
     const double Hbar = 0.5 * (L.h + R.h);
     const double gH = g * Hbar;
     const double dZ = R.z - L.z;
     const double w = R.Pi - L.Pi + gH * dZ;
     const double u_est = 0.5 * (L.un + R.un) - w * (0.5 * inv_af);
     const double hbu = Hbar * u_est;
-    const double fl = B_FLOOR * a_f;
-    // b^2 = max(bL^2, bR^2, hbu^2, fl^2); ib names the maximum
-    const double m01 = dmax(L.b2, R.b2), m23 = fmax(hbu * hbu, fl * fl);
+    const double fl2 = B_FLOOR2 * af2;                   // (B_FLOOR a_f)^2
+    // b^2 = max(bL^2, bR^2, hbu^2, fl2); ib names the maximum
+    const double m01 = dmax(L.b2, R.b2), m23 = fmax(hbu * hbu, fl2);
     const double b2 = dmax(m01, m23);
-    const int ib = m01 >= m23 ? (L.b2 >= R.b2 ? 0 : 1) : (hbu * hbu >= fl * fl ? 2 : 3);
+    const int ib = m01 >= m23 ? (L.b2 >= R.b2 ? 0 : 1) : (hbu * hbu >= fl2 ? 2 : 3);
     const double b = fsqrt(b2);
     const double A2 = af2 + b2;
     const double inv_a = frsq(A2);
@@ -121,8 +120,8 @@ __device__ __forceinline__ void iface_vjp(const Side& L, const Side& R, double g
     const double Fh = fdiv(u0, tau0);
 
     // ---- reverse ------------------------------------------------------
-    Lb = SideAdj{0, 0, 0, 0, 0, 0, 0, 0, 0};
-    Rb = SideAdj{0, 0, 0, 0, 0, 0, 0, 0, 0};
+    Lb = SideAdj{0, 0, 0, 0, 0, 0, 0, 0};
+    Rb = SideAdj{0, 0, 0, 0, 0, 0, 0, 0};
     // F_hu^{L,R} = P0 + gH (Z0 - z_{L,R}), F_ht = F_h vt0, F_z = O0
     const double P0b = Fb.FhuL + Fb.FhuR;
     double gHb = Fb.FhuL * (Z0 - L.z) + Fb.FhuR * (Z0 - R.z);
@@ -288,12 +287,11 @@ __device__ __forceinline__ void iface_vjp(const Side& L, const Side& R, double g
     const double A2b = 0.5 * ab * inv_a;
     af2b += A2b;
     double b2b = A2b + 0.5 * bb * frcp(b);
-    // b2 = max(bL2, bR2, hbu^2, fl^2)
+    // b2 = max(bL2, bR2, hbu^2, B_FLOOR^2 af2)
     add_if(Lb.b2, ib == 0, b2b);
     add_if(Rb.b2, ib == 1, b2b);
     const double hbub = ib == 2 ? 2.0 * hbu * b2b : 0.0;
-    const double flb = ib == 3 ? 2.0 * fl * b2b : 0.0;
-    double a_fb = B_FLOOR * flb;
+    add_if(af2b, ib == 3, B_FLOOR2 * b2b);
     // hbu = Hbar u_est
     Hbarb += hbub * u_est;
     const double u_estb = hbub * Hbar;
@@ -307,10 +305,8 @@ __device__ __forceinline__ void iface_vjp(const Side& L, const Side& R, double g
     Lb.Pi -= wb;
     gHb += wb * dZ;
     dZb += wb * gH;
-    // inv_af = 1 / a_f ; a_f = max(aK)
-    a_fb -= inv_afb * inv_af * inv_af;
-    add_if(Lb.aK, afL, a_fb);
-    add_if(Rb.aK, !afL, a_fb);
+    // inv_af = 1 / a_f
+    const double a_fb = -inv_afb * inv_af * inv_af;
     // dZ = zR - zL
     Rb.z += dZb;
     Lb.z -= dZb;
@@ -318,8 +314,9 @@ __device__ __forceinline__ void iface_vjp(const Side& L, const Side& R, double g
     Hbarb += g * gHb;
     Lb.h += 0.5 * Hbarb;
     Rb.h += 0.5 * Hbarb;
-    // af2 = g hmax^3
-    const double hmaxb = af2b * 3.0 * g * hmax * hmax;
+    // af2 = g hmax^3 ; a_f = hmax sqrt(g hmax), whose derivative
+    // 1.5 sqrt(g hmax) is 1.5 g hmax^2 / a_f
+    const double hmaxb = (af2b * 3.0 + a_fb * 1.5 * inv_af) * g * hmax * hmax;
     add_if(Lb.h, hmaxL, hmaxb);
     add_if(Rb.h, !hmaxL, hmaxb);
 }
@@ -388,9 +385,8 @@ __device__ __forceinline__ void project_vjp_grass(const Model& M, double h, doub
     hub += ub * tau;
     hvb += vb * tau;
     double taub = cb.tau + ub * hu + vb * hv;
-    // Pi = g h^2 / 2 ; aK = h sqrt(g h) ; tau = 1 / h
+    // Pi = g h^2 / 2 ; tau = 1 / h
     hb += cb.Pi * g * h;
-    hb += cb.aK * 1.5 * fsqrt(g * h);
     hb -= taub * tau * tau;
     zb = cb.z;
 }

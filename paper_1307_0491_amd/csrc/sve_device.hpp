@@ -41,6 +41,9 @@ enum { BCW = 0, BCE = 1, BCS = 2, BCN = 3 };
 enum : unsigned { ERR_POS = 1u, ERR_ORD = 2u, ERR_NONFIN = 4u };
 
 constexpr double B_FLOOR = 1e-14;
+// The floor enters as (B_FLOOR a_f)^2 with a_f = max(h sqrt(g h)) over the two
+// cells, i.e. B_FLOOR^2 g max(h)^3: the interface's a_f^2, already formed.
+constexpr double B_FLOOR2 = B_FLOOR * B_FLOOR;
 
 // ---------------------------------------------------------------------------
 // Reciprocal, division and square root for positive normal operands.
@@ -209,12 +212,12 @@ struct Cell {
     double tau, u, v, Pi;    // 1/h, velocities, pressure g h^2/2
     double qx, qy;           // bedload flux vector
     double bx2, by2;         // (h u)^2 + g h^2 dqx/du, (h v)^2 + g h^2 dqy/dv
-    double aK, inv_aK;       // h sqrt(g h) and its inverse
+    double inv_aK;           // 1 / (h sqrt(g h))
 };
 
 // One side of an interface seen along its normal.
 struct Side {
-    double h, tau, un, ut, Pi, z, q, b2, aK, inv_aK;
+    double h, tau, un, ut, Pi, z, q, b2, inv_aK;
 };
 
 struct Flux {
@@ -222,10 +225,10 @@ struct Flux {
 };
 
 __device__ __forceinline__ Side side_x(const Cell& c) {
-    return Side{c.h, c.tau, c.u, c.v, c.Pi, c.z, c.qx, c.bx2, c.aK, c.inv_aK};
+    return Side{c.h, c.tau, c.u, c.v, c.Pi, c.z, c.qx, c.bx2, c.inv_aK};
 }
 __device__ __forceinline__ Side side_y(const Cell& c) {
-    return Side{c.h, c.tau, c.v, c.u, c.Pi, c.z, c.qy, c.by2, c.aK, c.inv_aK};
+    return Side{c.h, c.tau, c.v, c.u, c.Pi, c.z, c.qy, c.by2, c.inv_aK};
 }
 
 // ---------------------------------------------------------------------------
@@ -347,15 +350,14 @@ __device__ __forceinline__ Cell project(const Model& M, double h, double hu,
     c.hu = hu;
     c.hv = hv;
     c.z = z;
-    // one reciprocal square root gives 1/sqrt(g h), hence 1/h = g r^2,
-    // sqrt(g h) = g h r and 1/(h sqrt(g h)) = r / h
+    // one reciprocal square root gives 1/sqrt(g h), hence 1/h = g r^2
+    // and 1/(h sqrt(g h)) = r / h
     const double gh = M.g * h;
     const double r = frsq(gh);
     c.tau = M.g * (r * r);
     c.u = hu * c.tau;
     c.v = hv * c.tau;
     c.Pi = 0.5 * gh * h;
-    c.aK = h * (gh * r);
     c.inv_aK = c.tau * r;
     double bx, by;
     closure<CL>(M, h, c.u, c.v, Ag, c.qx, c.qy, bx, by);
@@ -376,15 +378,13 @@ __device__ __forceinline__ Celer celerities(const Side& L, const Side& R, double
     Celer C;
     const double hmax = dmax(L.h, R.h);
     C.af2 = g * (hmax * hmax * hmax);
-    const double inv_af = dmin(L.inv_aK, R.inv_aK);       // 1 / max(aK)
-    const double a_f = dmax(L.aK, R.aK);
+    const double inv_af = dmin(L.inv_aK, R.inv_aK);       // 1 / max(h sqrt(g h))
     C.Hbar = 0.5 * (L.h + R.h);
     C.gHbar = g * C.Hbar;
     C.dZ = R.z - L.z;
     const double u_est = 0.5 * (L.un + R.un) - (R.Pi - L.Pi + C.gHbar * C.dZ) * (0.5 * inv_af);
     const double hbu = C.Hbar * u_est;
-    const double fl = B_FLOOR * a_f;
-    const double b2 = dmax(dmax(L.b2, R.b2), fmax(hbu * hbu, fl * fl));
+    const double b2 = dmax(dmax(L.b2, R.b2), fmax(hbu * hbu, B_FLOOR2 * C.af2));
     C.b = fsqrt(b2);
     const double A2 = C.af2 + b2;
     C.inv_a = frsq(A2);
@@ -401,13 +401,11 @@ __device__ __forceinline__ double iface_speed(const Side& L, const Side& R, doub
     const double hmax = dmax(L.h, R.h);
     const double af2 = g * (hmax * hmax * hmax);
     const double inv_af = dmin(L.inv_aK, R.inv_aK);
-    const double a_f = dmax(L.aK, R.aK);
     const double Hbar = 0.5 * (L.h + R.h);
     const double dZ = R.z - L.z;
     const double u_est = 0.5 * (L.un + R.un) - (R.Pi - L.Pi + (g * Hbar) * dZ) * (0.5 * inv_af);
     const double hbu = Hbar * u_est;
-    const double fl = B_FLOOR * a_f;
-    const double b2 = dmax(dmax(L.b2, R.b2), fmax(hbu * hbu, fl * fl));
+    const double b2 = dmax(dmax(L.b2, R.b2), fmax(hbu * hbu, B_FLOOR2 * af2));
     const double a = fsqrt(af2 + b2);
     return fmax(fabs(L.un - a * L.tau), fabs(R.un + a * R.tau));
 }

@@ -85,7 +85,6 @@ __device__ __forceinline__ Side next_side_x(const Cell& c) {
     s.z = dpp<DPP_NEXT>(c.z);
     s.q = dpp<DPP_NEXT>(c.qx);
     s.b2 = dpp<DPP_NEXT>(c.bx2);
-    s.aK = dpp<DPP_NEXT>(c.aK);
     s.inv_aK = dpp<DPP_NEXT>(c.inv_aK);
     return s;
 }
@@ -101,7 +100,6 @@ __device__ __forceinline__ Side next_speed_side(const Side& c) {
     s.z = dpp<DPP_NEXT>(c.z);
     s.q = 0.0;
     s.b2 = dpp<DPP_NEXT>(c.b2);
-    s.aK = dpp<DPP_NEXT>(c.aK);
     s.inv_aK = dpp<DPP_NEXT>(c.inv_aK);
     return s;
 }
@@ -239,7 +237,7 @@ __device__ __forceinline__ Side ghost_side_y(const Model& M, int side, const Sid
 
 // Per-lane state carried from one row to the next.
 struct RowCarry {
-    double h, tau, u, v, Pi, z, qy, by2, aK, inv, hu, hv, ag;   // projected row r-1
+    double h, tau, u, v, Pi, z, qy, by2, inv, hu, hv, ag;       // projected row r-1
     double dXh, dXm, dXt, dXz;                                 // x-flux differences, row r-1
     unsigned eX, eY;
     double Yh, Yt, YR, Yz;                                     // y-flux below row r-1
@@ -310,7 +308,7 @@ __device__ __forceinline__ void fused_tile(const Model& M, const StateView<T>& S
             eXn = e | dpp_u<DPP_PREV>(e);
         }
         Flux Y;
-        const Side Ls{c.h, c.tau, c.v, c.u, c.Pi, c.z, c.qy, c.by2, c.aK, c.inv};
+        const Side Ls{c.h, c.tau, c.v, c.u, c.Pi, c.z, c.qy, c.by2, c.inv};
         const unsigned eY = iface_flux(Ls, side_y(P), M.g, Y);
         if (do_upd.value) {
             const int ru = r - 1;
@@ -375,7 +373,7 @@ __device__ __forceinline__ void fused_tile(const Model& M, const StateView<T>& S
             }
         }
         c.h = P.h; c.tau = P.tau; c.u = P.u; c.v = P.v; c.Pi = P.Pi; c.z = P.z; c.qy = P.qy;
-        c.by2 = P.by2; c.aK = P.aK; c.inv = P.inv_aK; c.hu = P.hu; c.hv = P.hv; c.ag = cur.ag;
+        c.by2 = P.by2; c.inv = P.inv_aK; c.hu = P.hu; c.hv = P.hv; c.ag = cur.ag;
         c.dXh = dXh; c.dXm = dXm; c.dXt = dXt; c.dXz = dXz; c.eX = eXn; c.eY = eY;
         c.Yh = Y.Fh; c.Yt = Y.Fht; c.YR = Y.FhuR; c.Yz = Y.Fz;
     };
@@ -400,7 +398,7 @@ __device__ __forceinline__ void fused_tile(const Model& M, const StateView<T>& S
     {
         const Cell P = project<CL>(M, w.h, w.hu, w.hv, w.z, w.ag);
         c.h = P.h; c.tau = P.tau; c.u = P.u; c.v = P.v; c.Pi = P.Pi; c.z = P.z; c.qy = P.qy;
-        c.by2 = P.by2; c.aK = P.aK; c.inv = P.inv_aK; c.hu = P.hu; c.hv = P.hv; c.ag = w.ag;
+        c.by2 = P.by2; c.inv = P.inv_aK; c.hu = P.hu; c.hv = P.hv; c.ag = w.ag;
     }
     row(c, cur, j0, Y_{}, N_{}, N_{}, N_{});                       // row j0: fluxes only
     cur = nxt;
