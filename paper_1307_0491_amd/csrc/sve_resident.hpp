@@ -4,8 +4,8 @@
 //
 // Per step: one pass over the interfaces gives the fluxes (into LDS) and
 // the outer wave speeds of the current state (reduced in LDS into the time
-// step), barrier, cell update into registers, barrier (error check), new
-// state into LDS, barrier.  The loop ends after n steps, or early when t
+// step), barrier, cell update in place (the old cells kept in registers),
+// barrier; on an error every thread writes its old cells back.  The loop ends after n steps, or early when t
 // reaches t_end (the remaining steps would leave the state unchanged) or on
 // an error (the state before the failing step is kept).
 #pragma once
@@ -151,38 +151,45 @@ k_resident_1d(Model M, StateView<T> S, StateView<T> D, const double* __restrict_
             tnew = t + dt;
         }
         const double lx = dt / M.dx;
-        // new state in registers (constant indices after unrolling) until
-        // the step is known to be free of errors
-        double nh[RES_PER_THREAD], nhu[RES_PER_THREAD], nz[RES_PER_THREAD];
+        // new state written in place (each thread reads and writes only its
+        // own cells here); the old state stays in registers (constant
+        // indices after unrolling) until the step is known to be free of
+        // errors, and is written back if it is not
+        double oh[RES_PER_THREAD], ohu[RES_PER_THREAD], oz[RES_PER_THREAD];
 #pragma unroll
         for (int c = 0; c < RES_PER_THREAD; ++c) {
             const int i = threadIdx.x + c * RES_BLOCK;
             if (i >= nx) continue;
-            double hn = L.h[i] - lx * (L.Fh[i + 1] - L.Fh[i]);
-            double hun = L.hu[i] - lx * (L.FL[i + 1] - L.FR[i]);
-            double zn = L.z[i] - lx * (L.Fz[i + 1] - L.Fz[i]);
+            oh[c] = L.h[i];
+            ohu[c] = L.hu[i];
+            oz[c] = L.z[i];
+            double hn = oh[c] - lx * (L.Fh[i + 1] - L.Fh[i]);
+            double hun = ohu[c] - lx * (L.FL[i + 1] - L.FR[i]);
+            double zn = oz[c] - lx * (L.Fz[i + 1] - L.Fz[i]);
             if (M.momentum_friction) {
                 double hvn = 0.0;
                 apply_friction(M, dt, hn, hun, hvn);
             }
             e |= check_state(hn, hun, 0.0, zn);
-            nh[c] = hn;
-            nhu[c] = hun;
-            nz[c] = zn;
+            L.h[i] = (double)(T)hn;
+            L.hu[i] = (double)(T)hun;
+            L.z[i] = (double)(T)zn;
         }
         if (e) atomicOr(L.err, e);
         __syncthreads();
         err = *L.err;
-        if (err) break;                              // keep the state before this step
+        if (err) {                                   // keep the state before this step
 #pragma unroll
-        for (int c = 0; c < RES_PER_THREAD; ++c) {
-            const int i = threadIdx.x + c * RES_BLOCK;
-            if (i >= nx) continue;
-            L.h[i] = (double)(T)nh[c];
-            L.hu[i] = (double)(T)nhu[c];
-            L.z[i] = (double)(T)nz[c];
+            for (int c = 0; c < RES_PER_THREAD; ++c) {
+                const int i = threadIdx.x + c * RES_BLOCK;
+                if (i >= nx) continue;
+                L.h[i] = oh[c];
+                L.hu[i] = ohu[c];
+                L.z[i] = oz[c];
+            }
+            __syncthreads();
+            break;
         }
-        __syncthreads();
         t = tnew;
         dt_last = dt;
         S_known = false;
