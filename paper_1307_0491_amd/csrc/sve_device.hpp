@@ -94,6 +94,17 @@ __device__ __forceinline__ double fsqrt(double x) {
     return __builtin_fma(d, 0.5 * y, s);
 }
 
+// a b + c as one v_fma_f64.  In a Horner step fma(t, z, C) the compiler
+// picks the accumulating form v_fmac_f64 (the sum overwrites its addend)
+// and, since the coefficient C is a loop-invariant register it must keep,
+// copies C first: one extra instruction per step.  The three-operand form
+// needs no copy.
+__device__ __forceinline__ double vfma(double a, double b, double c) {
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
 // h^(-1/3) for finite h > 0.  With h = 2^(3q) hs, hs in [1/4, 2) (q from
 // the binary exponent), a single-precision estimate y = 2^(-log2(hs)/3)
 // from the hardware log2/exp2 (relative error about 2^-22) is refined by
@@ -138,15 +149,15 @@ __device__ __forceinline__ double gpow(double w, double p) {
     const double s = fdiv(m - 1.0, m + 1.0);
     const double z = s * s;
     double t = 1.0 / 21.0;
-    t = __builtin_fma(t, z, 1.0 / 19.0);
-    t = __builtin_fma(t, z, 1.0 / 17.0);
-    t = __builtin_fma(t, z, 1.0 / 15.0);
-    t = __builtin_fma(t, z, 1.0 / 13.0);
-    t = __builtin_fma(t, z, 1.0 / 11.0);
-    t = __builtin_fma(t, z, 1.0 / 9.0);
-    t = __builtin_fma(t, z, 1.0 / 7.0);
-    t = __builtin_fma(t, z, 1.0 / 5.0);
-    t = __builtin_fma(t, z, 1.0 / 3.0);
+    t = vfma(t, z, 1.0 / 19.0);
+    t = vfma(t, z, 1.0 / 17.0);
+    t = vfma(t, z, 1.0 / 15.0);
+    t = vfma(t, z, 1.0 / 13.0);
+    t = vfma(t, z, 1.0 / 11.0);
+    t = vfma(t, z, 1.0 / 9.0);
+    t = vfma(t, z, 1.0 / 7.0);
+    t = vfma(t, z, 1.0 / 5.0);
+    t = vfma(t, z, 1.0 / 3.0);
     t *= z;                                           // z/3 + z^2/5 + ... + z^10/21
     const double s2 = 2.0 * s;
     const double lnm = __builtin_fma(s2, t, s2);      // 2 atanh(s) = ln m
@@ -156,16 +167,16 @@ __device__ __forceinline__ double gpow(double w, double p) {
     const double kf = __builtin_rint(y * INV_LN2);
     const double r = __builtin_fma(-kf, LN2_LO, __builtin_fma(-kf, LN2_HI, y));
     double q = 1.0 / 6227020800.0;                    // 1/13!
-    q = __builtin_fma(q, r, 1.0 / 479001600.0);       // 1/12!
-    q = __builtin_fma(q, r, 1.0 / 39916800.0);
-    q = __builtin_fma(q, r, 1.0 / 3628800.0);
-    q = __builtin_fma(q, r, 1.0 / 362880.0);
-    q = __builtin_fma(q, r, 1.0 / 40320.0);
-    q = __builtin_fma(q, r, 1.0 / 5040.0);
-    q = __builtin_fma(q, r, 1.0 / 720.0);
-    q = __builtin_fma(q, r, 1.0 / 120.0);
-    q = __builtin_fma(q, r, 1.0 / 24.0);
-    q = __builtin_fma(q, r, 1.0 / 6.0);
+    q = vfma(q, r, 1.0 / 479001600.0);                // 1/12!
+    q = vfma(q, r, 1.0 / 39916800.0);
+    q = vfma(q, r, 1.0 / 3628800.0);
+    q = vfma(q, r, 1.0 / 362880.0);
+    q = vfma(q, r, 1.0 / 40320.0);
+    q = vfma(q, r, 1.0 / 5040.0);
+    q = vfma(q, r, 1.0 / 720.0);
+    q = vfma(q, r, 1.0 / 120.0);
+    q = vfma(q, r, 1.0 / 24.0);
+    q = vfma(q, r, 1.0 / 6.0);
     q = __builtin_fma(q, r, 0.5);
     q = __builtin_fma(q, r, 1.0);
     q = __builtin_fma(q, r, 1.0);
