@@ -155,4 +155,9 @@ def test_1d_resident_error_keeps_state(sve):
     kept, tk, _, nk = s.get_state()
     assert nk == ng and tk == tg
     assert kept[0][200] == -1.0
+    # the failing step wrote every cell before the error was known; all of
+    # them are back to the state before it
+    good[0][200] = -1.0
+    for a, b in zip(kept, good):
+        assert np.array_equal(a, b)
     s.close()

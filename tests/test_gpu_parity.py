@@ -132,6 +132,31 @@ def test_mpm_fp32_storage(sve, path):
         assert np.array_equal(a, a.astype(np.float32).astype(np.float64))
 
 
+@pytest.mark.parametrize("law,fric,coef", [("MPM", "STRICKLER", 40.0),
+                                           ("MPM", "MANNING", 0.03),
+                                           ("NIELSEN", "STRICKLER", 40.0)])
+@pytest.mark.parametrize("path", ["fused", "split"])
+def test_threshold_laws_wide_depth_range(sve, law, fric, coef, path):
+    """Threshold-law closures, whose shear stress scales with h^(-1/3), on
+    depths from 0.01 to 100 m (thirteen binades, every residue of the binary
+    exponent mod 3 of the cube-root range reduction), with transport above
+    the threshold in every cell.  Free boundaries on all sides."""
+    nx, ny = 90, 40
+    x = (np.arange(nx) + 0.5) / nx
+    h = np.tile(10.0 ** (-2.0 + 4.0 * x), (ny, 1))
+    rng = np.random.default_rng(3)
+    zb = (1e-3 * np.sin(2 * np.pi * np.arange(ny) / ny)[:, None] * np.ones((1, nx))
+          + 1e-4 * rng.standard_normal((ny, nx)))
+    hv = 0.2 * h * np.cos(2 * np.pi * np.arange(nx) / nx)[None, :]
+    case = dict(h=h, hu=2.0 * h, hv=hv, zb=zb, lx=900.0, ly=400.0)
+    p = mpm(sve, law=getattr(sve, "LAW_" + law), friction=getattr(sve, "FRIC_" + fric), coef=coef)
+    f, t, dtl, ns, o = run_pair(sve, case, p, [sve.BC(sve.BC_FREE)] * 4, 20, path=PATHS[path])
+    assert ns == 20
+    assert t == pytest.approx(o.t, rel=TOL64)
+    assert np.max(np.abs(o.state[3] - zb)) > 1e-5           # the bed moved
+    assert_fields_close(f, o.state, TOL64)
+
+
 @pytest.mark.parametrize("mg", [1.3, 2.5, 3.7])
 def test_general_exponent_wide_speed_range(sve, mg):
     """The general-exponent closure (|U|^(m_g-1) by exp and log series on
