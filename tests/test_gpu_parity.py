@@ -96,7 +96,7 @@ def test_fused_tile_rows_agree(sve, rows, path):
 
 
 @pytest.mark.parametrize("path", ["fused", "residual"])
-@pytest.mark.parametrize("rows", [1, 3, 0])
+@pytest.mark.parametrize("rows", [1, 2, 3, 4, 0])
 def test_fused_tile_rows_open_boundaries(sve, rows, path):
     """Tiles touching inflow and free boundaries, with uneven splits."""
     case = mpm_case(160, 70)
