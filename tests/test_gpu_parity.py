@@ -118,6 +118,40 @@ def test_mpm_strickler_inflow_free_fp64(sve, path):
     assert_fields_close(f, o.state, TOL64)
 
 
+@pytest.mark.parametrize("side", ["E", "S", "N", "WS"])
+@pytest.mark.parametrize("path", ["fused", "split"])
+def test_inflow_on_every_side(sve, side, path):
+    """The MPM channel mirrored or transposed so that the inflow boundary is
+    the east, south or north side (and west plus south at once): ghost
+    columns on the east edge of the last tile, ghost rows below the first
+    and above the last tile row."""
+    case = mpm_case(160, 70)
+    h, hu, hv, zb = case["h"], case["hu"], case["hv"], case["zb"]
+    lx, ly = case["lx"], case["ly"]
+    free = sve.BC(sve.BC_FREE)
+    if side == "E":
+        h, hu, hv, zb = h[:, ::-1], -hu[:, ::-1], hv[:, ::-1], zb[:, ::-1]
+        bcs = [free, sve.BC(sve.BC_INFLOW, 0.5, -2.0, 0.0), free, free]
+    elif side in ("S", "N"):
+        h, hu, hv, zb = h.T, hv.T, hu.T, zb.T
+        lx, ly = ly, lx
+        if side == "N":
+            h, hu, hv, zb = h[::-1], hu[::-1], -hv[::-1], zb[::-1]
+            bcs = [free, free, free, sve.BC(sve.BC_INFLOW, 0.5, 0.0, -2.0)]
+        else:
+            bcs = [free, free, sve.BC(sve.BC_INFLOW, 0.5, 0.0, 2.0), free]
+    else:
+        hv = hu.copy()
+        bcs = [sve.BC(sve.BC_INFLOW, 0.5, 2.0, 2.0), free, sve.BC(sve.BC_INFLOW, 0.5, 2.0, 2.0),
+               free]
+    case = dict(h=np.ascontiguousarray(h), hu=np.ascontiguousarray(hu),
+                hv=np.ascontiguousarray(hv), zb=np.ascontiguousarray(zb), lx=lx, ly=ly)
+    f, t, dtl, ns, o = run_pair(sve, case, mpm(sve), bcs, 40, path=PATHS[path])
+    assert ns == 40
+    assert t == pytest.approx(o.t, rel=TOL64)
+    assert_fields_close(f, o.state, TOL64)
+
+
 @pytest.mark.parametrize("path", ["fused", "residual"])
 def test_mpm_fp32_storage(sve, path):
     case = mpm_case(160, 70)
