@@ -119,7 +119,7 @@ def test_mpm_strickler_inflow_free_fp64(sve, path):
 
 
 @pytest.mark.parametrize("side", ["E", "S", "N", "WS"])
-@pytest.mark.parametrize("path", ["fused", "split"])
+@pytest.mark.parametrize("path", ["fused", "split", "residual"])
 def test_inflow_on_every_side(sve, side, path):
     """The MPM channel mirrored or transposed so that the inflow boundary is
     the east, south or north side (and west plus south at once): ghost
@@ -319,6 +319,20 @@ def test_antidune1d_inflow_free(sve):
     bcs = [sve.BC(sve.BC_INFLOW, 0.5, 1.7, 0.0), sve.BC(sve.BC_FREE)]
     for path in (sve.PATH_RESIDENT, sve.PATH_SPLIT):
         f, t, dtl, ns, o = run_pair(sve, case, grass(sve), bcs, 2000, path=path)
+        assert_fields_close(f, o.state, TOL64, names=("h", "hu", "z"))
+
+
+def test_antidune1d_mirrored_inflow_east(sve):
+    """The antidune channel mirrored: inflow through the east side, free
+    outflow through the west (the 1D kernels' ghost cell beyond the last
+    cell)."""
+    h, hu, zb, dx = W.antidune1d(1000)
+    case = dict(h=h[::-1].copy(), hu=-hu[::-1], zb=zb[::-1].copy(), lx=24.0)
+    bcs = [sve.BC(sve.BC_FREE), sve.BC(sve.BC_INFLOW, 0.5, -1.7, 0.0)]
+    for path in (sve.PATH_RESIDENT, sve.PATH_SPLIT):
+        f, t, dtl, ns, o = run_pair(sve, case, grass(sve), bcs, 2000, path=path)
+        assert ns == 2000
+        assert t == pytest.approx(o.t, rel=TOL64)
         assert_fields_close(f, o.state, TOL64, names=("h", "hu", "z"))
 
 
