@@ -336,6 +336,27 @@ def test_antidune1d_mirrored_inflow_east(sve):
         assert_fields_close(f, o.state, TOL64, names=("h", "hu", "z"))
 
 
+@pytest.mark.parametrize("law,fric,friction_src", [("MPM", "STRICKLER", 0), ("NIELSEN", "MANNING", 0),
+                                                  ("RIBBERINK", "DARCY", 0), ("CAMENEN", "STRICKLER", 0),
+                                                  ("MPM", "STRICKLER", 1)])
+def test_1d_threshold_laws_and_friction(sve, law, fric, friction_src):
+    """The threshold-law closures and the optional momentum friction in the
+    1D kernels (single-workgroup resident kernel and split path): the 1D
+    dune with transport above the threshold in every cell."""
+    h, hu, zb, dx = W.dune1d(1000)
+    case = dict(h=h, hu=hu, zb=zb, lx=1000.0)
+    coef = {"STRICKLER": 40.0, "MANNING": 0.025, "DARCY": 0.05}[fric]
+    p = mpm(sve, law=getattr(sve, "LAW_" + law), friction=getattr(sve, "FRIC_" + fric), coef=coef,
+            momentum_friction=friction_src)
+    bcs = [sve.BC(sve.BC_PERIODIC)] * 2
+    for path in (sve.PATH_RESIDENT, sve.PATH_SPLIT):
+        f, t, dtl, ns, o = run_pair(sve, case, p, bcs, 300, path=path)
+        assert ns == 300
+        assert t == pytest.approx(o.t, rel=TOL64)
+        assert np.max(np.abs(o.state[2] - zb)) > 1e-6           # the bed moved
+        assert_fields_close(f, o.state, TOL64, names=("h", "hu", "z"))
+
+
 def test_fp32_storage_1d(sve):
     h, hu, zb, dx = W.dune1d(1000)
     case = dict(h=h, hu=hu, zb=zb, lx=1000.0)
