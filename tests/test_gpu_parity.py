@@ -191,6 +191,23 @@ def test_threshold_laws_wide_depth_range(sve, law, fric, coef, path):
     assert_fields_close(f, o.state, TOL64)
 
 
+@pytest.mark.parametrize("mg", [3.0, 2.5])
+@pytest.mark.parametrize("path", ["fused", "split", "residual"])
+def test_fp32_storage_grass_2d(sve, mg, path):
+    """Float32 state storage with the Grass closures (m_g = 3 and the
+    general exponent) on the periodic dune, against the oracle's
+    float32-storage emulation."""
+    case = dune2d_case(130, 75)
+    case["hv"] = 0.5 * case["zb"]
+    f, t, dtl, ns, o = run_pair(sve, case, grass(sve, Ag=0.05, mg=mg), per(sve), 60,
+                                storage="fp32", path=PATHS[path])
+    assert ns == 60
+    assert t == pytest.approx(o.t, rel=TOL64)
+    assert_fields_close(f, o.state, TOL32)
+    for a in f:
+        assert np.array_equal(a, a.astype(np.float32).astype(np.float64))
+
+
 @pytest.mark.parametrize("mg", [1.3, 2.5, 3.7])
 def test_general_exponent_wide_speed_range(sve, mg):
     """The general-exponent closure (|U|^(m_g-1) by exp and log series on
