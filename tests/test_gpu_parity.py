@@ -191,6 +191,17 @@ def test_threshold_laws_wide_depth_range(sve, law, fric, coef, path):
     assert_fields_close(f, o.state, TOL64)
 
 
+@pytest.mark.parametrize("path", ["fused", "split", "residual"])
+def test_dune2d_to_t_end(sve, path):
+    """A 2D run stopped at t_end inside a call: the last step is clipped to
+    land on t_end and the remaining steps leave the state unchanged."""
+    case = dune2d_case(130, 75)
+    f, t, dtl, ns, o = run_pair(sve, case, grass(sve, Ag=0.05), per(sve), 400,
+                                path=PATHS[path], t_end=20.0)
+    assert t == 20.0 and o.t == 20.0
+    assert_fields_close(f, o.state, TOL64)
+
+
 @pytest.mark.parametrize("mg", [3.0, 2.5])
 @pytest.mark.parametrize("path", ["fused", "split", "residual"])
 def test_fp32_storage_grass_2d(sve, mg, path):
@@ -371,6 +382,19 @@ def test_1d_threshold_laws_and_friction(sve, law, fric, friction_src):
         assert ns == 300
         assert t == pytest.approx(o.t, rel=TOL64)
         assert np.max(np.abs(o.state[2] - zb)) > 1e-6           # the bed moved
+        assert_fields_close(f, o.state, TOL64, names=("h", "hu", "z"))
+
+
+def test_1d_ag_field(sve):
+    """A per-cell A_g field in the 1D kernels (resident and split)."""
+    h, hu, zb, dx = W.dune1d(1000)
+    case = dict(h=h, hu=hu, zb=zb, lx=1000.0)
+    rng = np.random.default_rng(9)
+    Ag = 1e-2 * (1.0 + 0.5 * rng.uniform(-1, 1, h.shape))
+    bcs = [sve.BC(sve.BC_PERIODIC)] * 2
+    for path in (sve.PATH_RESIDENT, sve.PATH_SPLIT):
+        f, t, dtl, ns, o = run_pair(sve, case, grass(sve, Ag=1e-2), bcs, 500, path=path, Ag=Ag)
+        assert t == pytest.approx(o.t, rel=TOL64)
         assert_fields_close(f, o.state, TOL64, names=("h", "hu", "z"))
 
 
