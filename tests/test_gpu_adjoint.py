@@ -215,3 +215,31 @@ def test_autograd_function_matches_adjoint(sve):
     pred = np.sum(gz * dz)
     assert abs(fd - pred) <= 1e-6 * abs(pred), (fd, pred)
     assert np.all(np.isfinite(gA)) and np.max(np.abs(gA)) > 0
+
+
+def test_unsupported_setups_are_rejected(sve):
+    """The adjoint covers 2D, FP64 storage, the Grass law, periodic
+    boundaries and no momentum friction; any other context is refused with
+    SVE_ERR_ARG before anything runs, and the solver itself still steps."""
+    h, hu, hv, z, Ag, lx, ly = random_state(20, 70, 4)
+    per4 = [sve.BC()] * 4
+    grass = sve.Params(law=sve.LAW_GRASS, A_g=2e-3, m_g=3.0)
+    cases = [
+        dict(params=grass, bcs=[sve.BC(sve.BC_FREE)] * 4, storage="fp64"),
+        dict(params=grass, bcs=per4, storage="fp32"),
+        dict(params=sve.Params(law=sve.LAW_MPM, friction=sve.FRIC_STRICKLER, fric_coef=40.0,
+                               d_s=1e-3, s=2.65, tau_cr=0.05), bcs=per4, storage="fp64"),
+        dict(params=sve.Params(law=sve.LAW_GRASS, A_g=2e-3, m_g=3.0, momentum_friction=1,
+                               friction=sve.FRIC_STRICKLER, fric_coef=40.0), bcs=per4,
+             storage="fp64"),
+    ]
+    from paper_1307_0491_amd.adjoint import AdjointRun
+    for c in cases:
+        s = sve.Solver(h, hu, z, hv, lx=lx, ly=ly, params=c["params"], bcs=c["bcs"],
+                       storage=c["storage"])
+        with pytest.raises(sve.SveError) as e:
+            AdjointRun(s).forward(4, 1e-3)
+        assert e.value.code == -1
+        s.step(2, 0.5)                      # the context is still usable
+        s.close()
+
