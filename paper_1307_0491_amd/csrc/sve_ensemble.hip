@@ -135,6 +135,8 @@ struct sve_ens {
 
 namespace {
 
+void drop_graph(sve_ens* e);
+
 int build_tiles(sve_ens* e, int rows) {
     if (e->dtiles && e->tiles_rows == rows) return SVE_OK;
     std::vector<int> order(e->n);
@@ -150,6 +152,8 @@ int build_tiles(sve_ens* e, int rows) {
         for (int y = 0; y < ty; ++y)
             for (int x = 0; x < tx; ++x) t.push_back(EnsTile{m, x, y, 0});
     }
+    // a captured graph holds the old tile list in its kernel arguments
+    drop_graph(e);
     if (e->dtiles) (void)hipFree(e->dtiles);
     e->dtiles = nullptr;
     if (hipMalloc((void**)&e->dtiles, t.size() * sizeof(EnsTile)) != hipSuccess) return SVE_ERR_HIP;
@@ -438,6 +442,10 @@ int sve_ens_autotune(sve_ens* e, int nprobe, double cfl, int* rows, int* mode) {
         hipStreamSynchronize(e->stream) != hipSuccess)
         return SVE_ERR_HIP;
     const long long n_saved = e->nsteps;
+    // a member that fails during a probe marks fail_step and sticky; both
+    // are rewound with the state
+    const std::vector<int> fail_saved = e->fail_step;
+    const int sticky_saved = e->sticky;
     int base_saved = 0;
     if (hipMemcpy(&base_saved, e->dbase, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
         return SVE_ERR_HIP;
@@ -450,6 +458,8 @@ int sve_ens_autotune(sve_ens* e, int nprobe, double cfl, int* rows, int* mode) {
                                  e->stream) == hipSuccess &&
                   hipStreamSynchronize(e->stream) == hipSuccess;
         e->nsteps = n_saved;
+        e->fail_step = fail_saved;
+        e->sticky = sticky_saved;
         return ok;
     };
     const int cand_rows[7] = {8, 16, 32, 48, 64, 96, 128};
