@@ -347,6 +347,66 @@ def test_momentum_friction_hand_value():
     assert np.allclose(o.hu, expected, rtol=1e-15)
 
 
+def test_momentum_friction_darcy_hand_value():
+    # Darcy-Weisbach slope S_f = f |U|^2 / (8 g h) (section "Bedload
+    # modelling"): -g h S_f = -(f |u| / (8 h)) hu, semi-implicit:
+    # hu / (1 + dt f |u| / (8 h)) on uniform flow over a flat bed
+    h0, q0, f = 8.0, 4.0, 0.1
+    p = O.Params(law=O.LAW_GRASS, A_g=0.0, friction=O.FRIC_DARCY, fric_coef=f,
+                 momentum_friction=1)
+    o = O.Oracle1D(np.full(10, h0), np.full(10, q0), np.zeros(10), 1.0, p, PER1)
+    o.step_fixed_dt(1, 0.1)
+    expected = q0 / (1.0 + 0.1 * f * 0.5 / (8.0 * h0))
+    assert np.allclose(o.hu, expected, rtol=1e-15)
+    assert expected != q0
+
+
+@pytest.mark.parametrize("fric,coef,phi", [
+    # |U| = 0.5 (u = 0.3, v = 0.4), h = 8 (h^(4/3) = 16), dt = 0.1
+    ("DARCY", 0.1, 0.1 * 0.5 / (8.0 * 8.0)),
+    ("MANNING", 0.5, 9.81 * 0.25 * 0.5 / 16.0),
+    ("STRICKLER", 2.0, 9.81 * 0.5 / (4.0 * 16.0)),
+])
+def test_momentum_friction_2d_hand_values(fric, coef, phi):
+    # both components are divided by 1 + dt phi(h, |U|), with the speed of
+    # the full velocity vector
+    h0 = 8.0
+    p = O.Params(law=O.LAW_GRASS, A_g=0.0, friction=getattr(O, "FRIC_" + fric),
+                 fric_coef=coef, momentum_friction=1)
+    h = np.full((6, 7), h0)
+    o = O.Oracle2D(h, 0.3 * h, 0.4 * h, np.zeros_like(h), 1.0, 2.0, p, PER2)
+    o.step_fixed_dt(1, 0.1)
+    den = 1.0 + 0.1 * phi
+    assert np.allclose(o.hu, 0.3 * h0 / den, rtol=1e-15)
+    assert np.allclose(o.hv, 0.4 * h0 / den, rtol=1e-15)
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_cfl_dt_hand_value_anisotropic_grid(transpose):
+    # Uniform flow (h, u, 0) over a flat bed without bedload on a grid with
+    # dx != dy.  The celerities of eq. "ab" with the reading's b: across an
+    # x-interface b = |h u| (cell bound, beta = 0), a^2 = g h^3 + (h u)^2, so
+    # the outer speed is S_x = |u| + sqrt(g h + u^2); across a y-interface
+    # the normal velocity is 0, b is the floor and S_y = sqrt(g h) (the floor
+    # changes it by 1e-28 relative).  dt = CFL / (S_x/dx + S_y/dy): each
+    # direction's speed is paired with its own spacing.
+    g, h0, u0, cfl, dx, dy = 9.81, 4.0, 2.0, 0.5, 1.0, 3.0
+    Sx = u0 + np.sqrt(g * h0 + u0 * u0)
+    Sy = np.sqrt(g * h0)
+    expected = cfl / (Sx / dx + Sy / dy)
+    h = np.full((9, 11), h0)
+    p = grass(Ag=0.0)
+    if transpose:
+        o = O.Oracle2D(h.T, 0 * h.T, u0 * h.T, 0 * h.T, dy, dx, p, PER2)
+    else:
+        o = O.Oracle2D(h, u0 * h, 0 * h, 0 * h, dx, dy, p, PER2)
+    assert o.cfl_dt(cfl) == pytest.approx(expected, rel=1e-14)
+    o.step(1, cfl)
+    assert o.t == pytest.approx(expected, rel=1e-14)
+    # the swapped pairing differs by far more than rounding
+    assert abs(cfl / (Sx / dy + Sy / dx) - expected) > 0.1 * expected
+
+
 def test_complex_step_tangent_matches_central_differences():
     rng = np.random.default_rng(4)
     h, hu, hv, zb, dx, dy = W.dune2d(12, 10, lx=100.0, ly=100.0)
