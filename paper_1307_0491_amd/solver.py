@@ -166,6 +166,13 @@ class Solver:
         fields = (outs[0], outs[1], outs[3]) if self.dim == 1 else tuple(outs)
         return fields, t.value, dtl.value, ns.value
 
+    def times(self):
+        """(t, dt_last, nsteps) without copying the state."""
+        t, dtl, ns = ctypes.c_double(), ctypes.c_double(), ctypes.c_longlong()
+        check(self.lib.sve_get_state(self._ctx, None, None, None, None, ctypes.byref(t),
+                                     ctypes.byref(dtl), ctypes.byref(ns)), "sve_get_state")
+        return t.value, dtl.value, ns.value
+
     def get_state_torch(self, device="cuda"):
         """Same as get_state with float64 torch tensors on the device."""
         torch = _torch()

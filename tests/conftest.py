@@ -20,3 +20,27 @@ def gpu_lib():
     import paper_1307_0491_amd as sve
     sve.require_device()
     return sve
+
+
+def pytest_runtest_setup(item):
+    try:
+        import gpu_helpers
+    except ImportError:
+        return
+    gpu_helpers.CURRENT_TEST = item.nodeid
+
+
+def pytest_sessionfinish(session, exitstatus):
+    """With SVE_PARITY_REPORT set, write every field comparison of the GPU
+    tests (relative errors per field, the transverse momentum also against
+    its own maximum) to that file as JSON."""
+    path = os.environ.get("SVE_PARITY_REPORT")
+    if not path:
+        return
+    try:
+        import gpu_helpers
+    except ImportError:
+        return
+    import json
+    with open(path, "w") as f:
+        json.dump(gpu_helpers.RECORDS, f)

@@ -17,6 +17,15 @@ configuration the benchmark times (default path, automatic tile split).
     output through device memory): two CFL steps; a window against the
     oracle run on that window with the same two time steps, and the sums of
     h and z_b conserved to rounding;
+  * the paper's 2D bump at its own size (4000 x 4000 cells, inflow through
+    the west side, free flow elsewhere, Grass A_g = 1, m_g = 3): 24 CFL
+    steps; three windows (on the bump, at the inflow side, at the free
+    north-east corner) against the oracle run on each window, with a halo
+    wider than the steps' reach and the library's time steps;
+  * the paper's 1D antidune at its own size (2400 cells, inflow / free
+    outflow) to T = 50 s: the states at 6, 10, 15, 30 and 50 s against the
+    oracle's stored in tests/golden/antidune1d_t50.npz, and the crest
+    moving upstream;
   * the 1024 x 1024 adjoint (2000 fixed-dt steps, sqrt(N) checkpoints):
     directional derivatives of the bed-misfit loss with respect to the
     initial bed and the A_g field against central differences of the
@@ -217,3 +226,71 @@ def test_adjoint_1024_directional_derivatives(sve):
         # the two step sizes agree (central differences: error ~ eps^2)
         assert abs(fd[1e-3] - fd[5e-4]) <= 4e-6 * abs(fd[5e-4]), (name, fd)
         assert abs(adj - fd[5e-4]) <= 1e-6 * abs(fd[5e-4]), (name, adj, fd)
+
+
+def test_paper_bump_4000_windows(sve):
+    n, nsteps, halo, w = 4000, 24, 26, 48
+    h, hu, hv, zb, dx, dy = W.dune2d(n, n, base=0.1)
+    p = sve.Params(law=sve.LAW_GRASS, A_g=1.0, m_g=3.0)
+    bcs = [sve.BC(sve.BC_INFLOW, 9.9, 10.0, 0.0), sve.BC(sve.BC_FREE), sve.BC(sve.BC_FREE),
+           sve.BC(sve.BC_FREE)]
+    s = sve.Solver(h, hu, zb, hv, lx=1000.0, ly=1000.0, params=p, bcs=bcs)
+    dts = []
+    for _ in range(nsteps):
+        s.step(1, 0.5)
+        dts.append(s.times()[1])
+    (gh, ghu, ghv, gz), t, dtl, ns = s.get_state()
+    s.close()
+    assert ns == nsteps and t == pytest.approx(sum(dts), rel=TOL64)
+    po = O.Params(law=O.LAW_GRASS, A_g=1.0, m_g=3.0)
+    free = O.BC(O.BC_FREE)
+    inflow = O.BC(O.BC_INFLOW, 9.9, 10.0, 0.0)
+    # (first row, first column) of the w x w window checked, and the rows /
+    # columns of the oracle's domain around it (the grid's own boundary
+    # where the window touches it, else a halo beyond the steps' reach)
+    cases = {
+        "bump": ((1950, 1250), (1950 - halo, 1950 + w + halo), (1250 - halo, 1250 + w + halo),
+                 (free,) * 4),
+        "inflow": ((2000, 0), (2000 - halo, 2000 + w + halo), (0, w + halo),
+                   (inflow, free, free, free)),
+        "corner": ((n - w, n - w), (n - w - halo, n), (n - w - halo, n), (free,) * 4),
+    }
+    for name, ((j0, i0), (ja, jb), (ia, ib), obcs) in cases.items():
+        sl = (slice(ja, jb), slice(ia, ib))
+        o = O.Oracle2D(h[sl], hu[sl], hv[sl], zb[sl], dx, dy, po, obcs)
+        for dt in dts:
+            o.step_fixed_dt(1, dt)
+        inner = (slice(j0, j0 + w), slice(i0, i0 + w))
+        oin = (slice(j0 - ja, j0 - ja + w), slice(i0 - ia, i0 - ia + w))
+        got = [g[inner] for g in (gh, ghu, ghv, gz)]
+        ref = [a[oin] for a in o.state]
+        assert_fields_close(got, ref, TOL64)
+        if name == "bump":
+            assert np.max(np.abs(ref[3] - zb[inner])) > 1e-4       # the bed moved
+            assert np.max(np.abs(ref[2])) > 1e-6                   # flow around the bump
+
+
+def test_antidune_2400_to_t50_against_stored_oracle(sve):
+    ref = np.load(os.path.join(GOLDEN, "antidune1d_t50.npz"))
+    h, hu, zb, dx = W.antidune1d(2400)
+    s = sve.Solver(h, hu, zb, lx=24.0, params=sve.Params(law=sve.LAW_GRASS, A_g=1e-3, m_g=3.0),
+                   bcs=[sve.BC(sve.BC_INFLOW, 0.5, 1.7, 0.0), sve.BC(sve.BC_FREE)])
+    x = (np.arange(2400) + 0.5) * dx
+    crest = [x[np.argmax(zb)]]
+    done = 0
+    for k, t_end in enumerate(ref["times"]):
+        n = int(ref[f"nsteps{k}"])
+        # exactly the oracle's number of real steps, the last one clipped to
+        # land on the snapshot time
+        t = s.step(n - done, 0.5, float(t_end))
+        done = n
+        (gh, ghu, gz), t2, dtl, ns = s.get_state()
+        assert t == float(t_end) and ns == n
+        assert dtl == pytest.approx(float(ref[f"dt_last{k}"]), rel=1e-9)
+        assert_fields_close((gh, ghu, gz), (ref[f"h{k}"], ref[f"hu{k}"], ref[f"zb{k}"]), TOL64,
+                            names=("h", "hu", "z"))
+        crest.append(x[np.argmax(gz)])
+    s.close()
+    # the antidune travels upstream (section "1D antidune evolution"): the
+    # crest of the GPU state moves toward the inflow between snapshots
+    assert all(b < a for a, b in zip(crest[:-1], crest[1:])), crest
