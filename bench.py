@@ -94,7 +94,7 @@ def workload():
     return h, hu, hv, zb
 
 
-def cpu_baseline(nsteps: int = 3):
+def cpu_baseline(nsteps: int = 20):
     """The oracle as it stands, on the host, over `nsteps` steps of the same
     2000 x 2000 grid (bounded sample of the workload)."""
     import oracle as O
@@ -108,6 +108,25 @@ def cpu_baseline(nsteps: int = 3):
             "kind": "oracle",
             "sample": f"{nsteps} CFL steps of the full {NX}x{NY} grid, numpy FP64, one process",
             "seconds": el, "host": host_cpu()}
+
+
+def cpu_baseline_1d(nsteps: int = 20000):
+    """The oracle on the 1D dune (1000 cells, periodic, CFL 0.5) over the
+    first `nsteps` of its 218 402 steps to T = 10000 s (bounded sample)."""
+    import oracle as O
+    import workloads as W
+    h, hu, zb, dx = W.dune1d(1000)
+    o = O.Oracle1D(h, hu, zb, dx, O.Params(law=O.LAW_GRASS, A_g=1e-3, m_g=3.0),
+                   (O.BC(), O.BC()))
+    t0 = time.perf_counter()
+    o.step(nsteps, 0.5, 10000.0)
+    el = time.perf_counter() - t0
+    rate = 1000.0 * nsteps / el
+    return {"value": rate, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"the first {nsteps} of the {DUNE1D_STEPS} CFL steps to T = 10000 s, "
+                      "numpy FP64, one process",
+            "seconds": el,
+            "full_run_s_extrapolated": 1000.0 * DUNE1D_STEPS / rate}
 
 
 def host_cpu():
@@ -250,8 +269,10 @@ def dune1d_leg(args, sve, torch):
 def run_to(s, t_end, cfl=0.5, chunk=1000):
     """Advance solver s to t_end; returns the number of steps that advanced
     the time (chunks of `chunk` steps while they stay clear of t_end, then
-    single steps, the last one clipped to land on t_end)."""
+    single steps, the last one clipped to land on t_end) and the summed
+    time between the HIP events around each call's launches (ms)."""
     t = s.step(1, cfl, t_end)
+    kern_ms = s.last_elapsed_ms()
     steps = 1
     dt = t
     while t < t_end:
@@ -262,8 +283,9 @@ def run_to(s, t_end, cfl=0.5, chunk=1000):
         else:
             t_new = s.step(1, cfl, t_end)
             steps += 1
+        kern_ms += s.last_elapsed_ms()
         t = t_new
-    return steps
+    return steps, kern_ms
 
 
 def paper2d_leg(args, sve, torch):
@@ -278,13 +300,14 @@ def paper2d_leg(args, sve, torch):
     bcs = [sve.BC(sve.BC_INFLOW, 9.9, 10.0, 0.0), sve.BC(sve.BC_FREE), sve.BC(sve.BC_FREE),
            sve.BC(sve.BC_FREE)]
     out = {"nx": n, "ny": n}
-    for ag, t_end in ((1.0, 500.0), (0.1, 1000.0)):
+    runs = ((0.1, 1000.0),) if args.paper_runs == "scaling" else ((1.0, 500.0), (0.1, 1000.0))
+    for ag, t_end in runs:
         s = sve.Solver(h, hu, zb, hv, lx=1000.0, ly=1000.0,
                        params=sve.Params(law=sve.LAW_GRASS, A_g=ag, m_g=3.0), bcs=bcs,
                        stream=sve.current_stream_handle())
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        steps = run_to(s, t_end)
+        steps, kern_ms = run_to(s, t_end)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         (gh, _, _, gz), t, _, _ = s.get_state()
@@ -293,6 +316,10 @@ def paper2d_leg(args, sve, torch):
         out[f"A_g={ag:g}"] = {
             "t_end": t, "steps": steps, "wall_s": wall,
             "cell_updates_per_s": n * n * steps / wall,
+            "ms_per_step": wall * 1e3 / steps,
+            "avg_launch_us": kern_ms * 1e3 / steps,
+            "hbm_frac": BYTES_PER_CELL_FP64 * n * n * steps / (kern_ms * 1e-3) / 1e9
+                        / HBM_PEAK_GBS,
             "zb_max": float(gz.max()), "zb_max_at_m": [float((k % n + 0.5) * dx),
                                                       float((k // n + 0.5) * dy)],
             "finite": bool(np.all(np.isfinite(gh)) and np.all(gh > 0))}
@@ -425,12 +452,15 @@ def main():
                     help="tile rows of the fused kernel (0: automatic)")
     ap.add_argument("--path", default="fused", choices=["fused", "split", "residual"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-steps", type=int, default=3)
-    ap.add_argument("--legs", default="main,mpm,dune1d,ensemble,adjoint",
+    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-1d-steps", type=int, default=20000)
+    ap.add_argument("--legs", default="main,mpm,dune1d,ensemble,adjoint,paper2d",
                     help="comma list of main, mpm, dune1d, ensemble, adjoint, paper2d "
-                         "(paper2d: the paper's 4000x4000 runs to T, about two minutes; "
-                         "not in the default list)")
+                         "(paper2d: the paper's 4000x4000 bump to T)")
     ap.add_argument("--paper-n", type=int, default=4000)
+    ap.add_argument("--paper-runs", default="scaling", choices=["scaling", "both"],
+                    help="scaling: A_g = 0.1 to T = 1000 s (the run of the paper's "
+                         "performance figure, about a minute); both: also A_g = 1 to T = 500 s")
     ap.add_argument("--mpm-steps", type=int, default=200)
     ap.add_argument("--mpm-warmup", type=int, default=10)
     ap.add_argument("--ens-members", type=int, default=256)
@@ -461,6 +491,19 @@ def main():
            "config": {"workload": "2D Grass dune, periodic, 2000x2000 cells on [0,1000]^2 m, "
                                   "A_g=1e-3, m_g=3, CFL 0.5, FP64",
                       "nx": NX, "ny": NY, "path": args.path, "tile_rows": args.rows}}
+    if args.copy_calib:
+        out["copy_calibration"] = copy_calibration(torch, args.copy_calib)
+    if "mpm" in legs:
+        out["mpm"] = mpm_leg(args, sve, torch)
+    if "dune1d" in legs:
+        out["dune1d"] = dune1d_leg(args, sve, torch)
+    if "ensemble" in legs:
+        out["ensemble"] = ensemble_leg(args, sve, torch)
+    if "adjoint" in legs:
+        out["adjoint"] = adjoint_leg(args, sve, torch)
+    if "paper2d" in legs:
+        out["paper2d"] = paper2d_leg(args, sve, torch)
+    # the main leg runs after the others, on a device at its working clock
     if "main" in legs:
         wall, kern_ms, t, ns, ok = main_leg(args, sve, torch)
         progress(f"main: {args.steps} steps in {wall:.3f} s")
@@ -502,21 +545,12 @@ def main():
         out["roofline"]["frac_of_measured_copy"] = achieved / cp
         if not ok:
             out["error"] = "non-finite or non-positive depth after the run"
-    if args.copy_calib:
-        out["copy_calibration"] = copy_calibration(torch, args.copy_calib)
-    if "mpm" in legs:
-        out["mpm"] = mpm_leg(args, sve, torch)
-    if "dune1d" in legs:
-        out["dune1d"] = dune1d_leg(args, sve, torch)
-    if "ensemble" in legs:
-        out["ensemble"] = ensemble_leg(args, sve, torch)
-    if "adjoint" in legs:
-        out["adjoint"] = adjoint_leg(args, sve, torch)
-    if "paper2d" in legs:
-        out["paper2d"] = paper2d_leg(args, sve, torch)
     if not args.no_cpu and "main" in legs:
         progress("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
+    if not args.no_cpu and "dune1d" in legs:
+        progress("cpu baseline 1D (oracle)")
+        out["dune1d"]["cpu_baseline"] = cpu_baseline_1d(args.cpu_1d_steps)
     print(json.dumps(out), flush=True)
 
 
