@@ -146,6 +146,44 @@ int sve_get_state_dev(sve_ctx *ctx, double *h, double *hu, double *hv,
                       double *zb, double *t, double *dt_last,
                       long long *nsteps);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): n CFL
+ * steps as sve_step, on a state held in caller device memory, with nothing
+ * allocated by the library (no context, no hipMalloc/hipFree, no
+ * allocating library routine).
+ *   Scope     2D grids, FP64 state, uniform A_g (p->A_g), the fused step
+ *             kernel with the automatic tile split, i.e. the arithmetic of
+ *             sve_step on a context created from the same arguments.
+ *   State     h, hu, hv, zb: the initial state (nx*ny doubles each, layout as
+ *             above, on the current device); they are also the second
+ *             buffer of the steps and are overwritten when n >= 2.
+ *             h_out .. zb_out: receive the state after the n steps.  The
+ *             eight arrays must not overlap.
+ *   Time      *t: the time of the initial state on entry, the time reached
+ *             on return; t_end > 0 clips the last step as for sve_step.
+ *             *dt_last (may be NULL) receives the last step's dt on success.
+ *   Stream    all work runs on `stream` (NULL: the default stream); the call
+ *             returns after synchronising it.
+ *   Scratch   the steps' control block (wave-speed maxima, times, error
+ *             word) lives in a fixed 4 KiB device array of the library, one
+ *             per GPU, held until the process ends; it is independent of
+ *             the grid size, so no grid is too large for it (grids beyond
+ *             the kernels' nx*ny <= 2^31 - 1 are rejected).  Every call on a
+ *             GPU uses that GPU's array and starts by resetting it: calls
+ *             that overlap on one GPU (from several host threads or
+ *             streams) race and must be serialised by the caller.
+ *   Errors    SVE_ERR_ARG for invalid arguments, overlapping arrays or an
+ *             input state that sve_init_state would refuse (non-finite,
+ *             h <= 0); a step error returns its code, with the last state
+ *             that completed in h_out .. zb_out and its time in *t.
+ */
+int sve_step_dev_noalloc(int nx, int ny, double Lx, double Ly, const sve_params *p,
+                         const sve_bc bc[4], double *h, double *hu, double *hv,
+                         double *zb, double *h_out, double *hu_out, double *hv_out,
+                         double *zb_out, int n, double cfl, double t_end, double *t,
+                         double *dt_last, void *stream);
+
 /* Release every device buffer of the context.  NULL is accepted. */
 int sve_destroy(sve_ctx *ctx);
 

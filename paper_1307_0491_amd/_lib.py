@@ -78,6 +78,8 @@ SIGNATURES = {
     "sve_set_tile_rows": (I, [P, I]),
     "sve_debug_poke": (I, [P, I, LL, D]),
     "sve_last_elapsed_ms": (I, [P, DP]),
+    "sve_step_dev_noalloc": (I, [I, I, D, D, ctypes.POINTER(SveParams), ctypes.POINTER(SveBC),
+                                 P, P, P, P, P, P, P, P, I, D, D, DP, DP, P]),
     "sve_adj_forward": (I, [P, I, D, I]),
     "sve_adj_backward": (I, [P, P, P, P]),
     "sve_adj_step_vjp": (I, [P, D, P, P, P]),

@@ -56,7 +56,9 @@ int code_from_bits(unsigned bits) {
     return SVE_OK;
 }
 
-int validate_params(const sve_params* p, int dim, const sve_bc* bc) {
+}  // namespace
+
+int sve::validate_params(const sve_params* p, int dim, const sve_bc* bc) {
     if (!p || !bc) return SVE_ERR_ARG;
     if (!(p->g > 0.0) || !std::isfinite(p->g)) return SVE_ERR_ARG;
     if (p->law < SVE_LAW_GRASS || p->law > SVE_LAW_CAMENEN) return SVE_ERR_ARG;
@@ -81,8 +83,6 @@ int validate_params(const sve_params* p, int dim, const sve_bc* bc) {
         return SVE_ERR_ARG;
     return SVE_OK;
 }
-
-}  // namespace
 
 Model sve::make_model(int nx, int ny, double Lx, double Ly, int dim, const sve_params* p,
                       const sve_bc* bc) {
@@ -136,18 +136,7 @@ namespace {
 
 template <typename T>
 void launch_speeds(sve_ctx* c, int buf, int slot) {
-    const Model& M = c->M;
-    const long long nint = (long long)(M.nx + 1) * M.ny +
-                           (M.dim == 2 ? (long long)M.nx * (M.ny + 1) : 0);
-    const unsigned blocks = (unsigned)((nint + SPEED_BLOCK - 1) / SPEED_BLOCK);
-    const int cl = closure_class(M);
-    auto kern = cl == CL_GRASS3 ? k_speeds<T, CL_GRASS3>
-              : cl == CL_GRASS1 ? k_speeds<T, CL_GRASS1>
-              : cl == CL_GRASSM ? k_speeds<T, CL_GRASSM>
-              : cl == CL_MPM    ? k_speeds<T, CL_MPM>
-                                : k_speeds<T, CL_THRESH>;
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(SPEED_BLOCK), 0, c->stream, M,
-                       view_of<T>(c, buf), (const double*)c->Ag, c->ctrl, slot);
+    launch_speeds_model<T>(c->M, view_of<T>(c, buf), c->Ag, c->ctrl, slot, c->stream);
 }
 
 template <typename T>

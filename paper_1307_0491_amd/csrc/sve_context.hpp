@@ -40,6 +40,9 @@ struct sve_ctx {
 namespace sve {
 Model make_model(int nx, int ny, double Lx, double Ly, int dim, const sve_params* p,
                  const sve_bc* bc);
+// SVE_OK when the model parameters and boundary conditions are valid for a
+// grid of dimension `dim`, else SVE_ERR_ARG.
+int validate_params(const sve_params* p, int dim, const sve_bc* bc);
 }
 
 // Frees the adjoint buffers of a context (defined with the adjoint).

@@ -72,6 +72,23 @@ k_speeds(Model M, StateView<T> S, const double* __restrict__ Agf, Ctrl* ctrl, in
     }
 }
 
+// Outer wave speeds of the state S into slot `slot` of the control block
+// (one thread per interface).
+template <typename T>
+void launch_speeds_model(const Model& M, StateView<T> S, const double* Ag, Ctrl* ctrl, int slot,
+                         hipStream_t stream) {
+    const long long nint = (long long)(M.nx + 1) * M.ny +
+                           (M.dim == 2 ? (long long)M.nx * (M.ny + 1) : 0);
+    const unsigned blocks = (unsigned)((nint + SPEED_BLOCK - 1) / SPEED_BLOCK);
+    const int cl = closure_class(M);
+    auto kern = cl == CL_GRASS3 ? k_speeds<T, CL_GRASS3>
+              : cl == CL_GRASS1 ? k_speeds<T, CL_GRASS1>
+              : cl == CL_GRASSM ? k_speeds<T, CL_GRASSM>
+              : cl == CL_MPM    ? k_speeds<T, CL_MPM>
+                                : k_speeds<T, CL_THRESH>;
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(SPEED_BLOCK), 0, stream, M, S, Ag, ctrl, slot);
+}
+
 // Per-step bookkeeping done by one thread of step n: time of step n+1,
 // last dt, and clearing of the maxima slot used by step n+2.
 __device__ __forceinline__ void step_bookkeeping(Ctrl* ctrl, int n, const StepTime& st) {
