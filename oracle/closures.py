@@ -58,6 +58,7 @@ class Params:
     s: float = 2.65          # rho_s / rho
     tau_cr: float = 0.05     # critical Shields number
     momentum_friction: int = 0  # 1: semi-implicit -g h S_f in momentum
+    reconstruction: int = 0  # 1: hydrostatic reconstruction at interfaces
 
 
 def _re(x):

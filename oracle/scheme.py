@@ -23,6 +23,29 @@ Riemann solutions; 2D by the method of lines on a structured mesh, section
 Relaxation variables are never stored: they are projected again from the
 state at the start of every step.
 
+Well-balanced variant (Params.reconstruction = 1).  The paper notes that
+the scheme is not well balanced (a lake at rest over a varying bed does not
+stay at rest) and names well balancing as future work, citing among others
+the hydrostatic reconstruction of Audusse, Bouchut, Bristeau, Klein and
+Perthame (2004).  That method, applied with the relaxation solver above as
+the interface solver:
+  * at each interface, z* = max(z_L, z_R) and the reconstructed depths
+    h_L* = max(0, h_L + z_L - z*), h_R* = max(0, h_R + z_R - z*), the
+    velocities kept: U_L* = (h_L*, h_L* u_L, h_L* v_L), likewise U_R*;
+  * each reconstructed state is projected (closure at h*, U) and the
+    relaxation Riemann problem is solved between them with the bed z* on
+    both sides (the bed step is carried by the reconstruction; the sediment
+    waves still move the bed through Omega);
+  * the momentum fluxes seen by the two cells get the hydrostatic
+    corrections g/2 (h_L^2 - h_L*^2) (left cell) and g/2 (h_R^2 - h_R*^2)
+    (right cell); the mass, transverse-momentum and bed fluxes are those
+    of the reconstructed problem.
+A lake at rest (u = v = 0, h + z_b constant) gives equal reconstructed
+states at every interface, hence constant Riemann solutions, zero mass and
+bed fluxes and momentum fluxes g h^2/2 that cancel in each cell: it is kept
+for every bedload law and exponent.  On a flat bed the variant is the
+scheme itself.
+
 Storage "fp32" emulates float32 state storage with float64 arithmetic: the
 state is rounded to float32 at initialisation and after every step.
 """
@@ -34,7 +57,7 @@ import numpy as np
 
 from .closures import Params, closure, friction_factor
 from .riemann import (CellState, interface_solve, project, ERR_NONFINITE,
-                      ERR_POSITIVITY, _re)
+                      ERR_POSITIVITY, _max, _re)
 
 BC_PERIODIC = 0
 BC_FREE = 1
@@ -120,6 +143,38 @@ def _project_padded(Pd: dict, p: Params):
     return project(h, hu, hv, z, qx, qy, bx, by, p.g)
 
 
+def _reconstructed_sides(Pd: dict, p: Params, normal: str, slL, slR):
+    """Hydrostatic reconstruction between the padded cells slL (left) and
+    slR (right): the projected reconstructed states and the depths needed
+    by the momentum corrections."""
+    hL, zL = Pd["h"][slL], Pd["z"][slL]
+    hR, zR = Pd["h"][slR], Pd["z"][slR]
+    zs = _max(zL, zR)
+    hLs = _max(hL + zL - zs, 0.0 * hL)
+    hRs = _max(hR + zR - zs, 0.0 * hR)
+    out = []
+    for sl, hs in ((slL, hLs), (slR, hRs)):
+        u = Pd["hu"][sl] / Pd["h"][sl]
+        v = Pd["hv"][sl] / Pd["h"][sl]
+        fields = dict(h=hs, hu=hs * u, hv=hs * v, z=zs)
+        if "Ag" in Pd:
+            fields["Ag"] = Pd["Ag"][sl]
+        P = _project_padded(fields, p)
+        out.append(_cells(P, normal, Ellipsis))
+    return out[0], out[1], hL, hLs, hR, hRs
+
+
+def _reconstructed_solve(Pd: dict, p: Params, normal: str, slL, slR):
+    """Interface results of the well-balanced variant: the relaxation
+    Riemann problem between the reconstructed states, with the hydrostatic
+    corrections added to the momentum fluxes of the two cells."""
+    L, R, hL, hLs, hR, hRs = _reconstructed_sides(Pd, p, normal, slL, slR)
+    res = interface_solve(L, R, p.g)
+    res.FhuL = res.FhuL + 0.5 * p.g * (hL * hL - hLs * hLs)
+    res.FhuR = res.FhuR + 0.5 * p.g * (hR * hR - hRs * hRs)
+    return res
+
+
 def fluxes_2d(h, hu, hv, z, p: Params, bcs, Ag=None):
     """All x-interface results (ny, nx+1) and y-interface results (ny+1, nx).
     x-interface m of row j lies between cells m-1 and m; y-interface m of
@@ -128,8 +183,14 @@ def fluxes_2d(h, hu, hv, z, p: Params, bcs, Ag=None):
     if Ag is not None:
         fields["Ag"] = Ag
     Pd = pad2d(fields, bcs)
-    P = _project_padded(Pd, p)
     ny, nx = h.shape
+    if p.reconstruction:
+        X = _reconstructed_solve(Pd, p, "x", (slice(1, ny + 1), slice(0, nx + 1)),
+                                 (slice(1, ny + 1), slice(1, nx + 2)))
+        Y = _reconstructed_solve(Pd, p, "y", (slice(0, ny + 1), slice(1, nx + 1)),
+                                 (slice(1, ny + 2), slice(1, nx + 1)))
+        return X, Y
+    P = _project_padded(Pd, p)
     Lx = _cells(P, "x", (slice(1, ny + 1), slice(0, nx + 1)))
     Rx = _cells(P, "x", (slice(1, ny + 1), slice(1, nx + 2)))
     Ly = _cells(P, "y", (slice(0, ny + 1), slice(1, nx + 1)))
@@ -143,8 +204,10 @@ def fluxes_1d(h, hu, z, p: Params, bcs, Ag=None):
     if Ag is not None:
         fields["Ag"] = Ag
     Pd = pad1d(fields, bcs)
-    P = _project_padded(Pd, p)
     nx = h.shape[0]
+    if p.reconstruction:
+        return _reconstructed_solve(Pd, p, "x", slice(0, nx + 1), slice(1, nx + 2))
+    P = _project_padded(Pd, p)
     L = _cells(P, "x", slice(0, nx + 1))
     R = _cells(P, "x", slice(1, nx + 2))
     return interface_solve(L, R, p.g)
