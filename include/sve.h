@@ -84,7 +84,26 @@ typedef struct sve_params {
     double tau_cr;           /* critical Shields number (0.05 in the paper)    */
     int    momentum_friction;/* 0: eq. "bedload system" as printed; 1: adds
                                 a semi-implicit -g h S_f momentum source       */
+    int    reconstruction;   /* 0: the paper's scheme; 1: well-balanced variant
+                                (hydrostatic reconstruction, see below)        */
 } sve_params;
+
+/*
+ * Well-balanced variant (reconstruction = 1).  The paper's scheme is not
+ * well balanced (section "Parallelization": a lake at rest over a varying
+ * bed does not stay at rest) and well balancing is its stated future work
+ * (section "Conclusions and perspectives").  The variant applies the
+ * hydrostatic reconstruction of Audusse, Bouchut, Bristeau, Klein and
+ * Perthame (2004), which the paper cites, with the relaxation solver as the
+ * interface solver: at each interface z* = max(z_L, z_R) and
+ * h* = max(0, h + z_b - z*) on each side (velocities kept); the relaxation
+ * Riemann problem is solved between the projected reconstructed states on
+ * the bed z*, and each cell's momentum flux gets g/2 (h^2 - h*^2).  A lake at
+ * rest then stays at rest for every bedload law and exponent; on a flat bed
+ * the variant is the paper's scheme.  Supported by sve_step and
+ * sve_step_fixed_dt on every path (2D steps run on the split kernels); the
+ * adjoint, the ensemble and sve_step_dev_noalloc return SVE_ERR_ARG for it.
+ */
 
 typedef struct sve_bc {
     int    kind;             /* SVE_BC_*                                       */

@@ -41,9 +41,10 @@ typedef struct sve_ens sve_ens;
 
 /*
  * Create an ensemble of n members (n >= 1).  p: shared parameters (law must
- * be SVE_LAW_GRASS; g is used; each member's A_g and m_g replace p's).
- * stream: hipStream_t for all work (may be NULL).  Returns SVE_ERR_ARG for
- * invalid members (size, h <= 0, m_g outside [1, 4]).
+ * be SVE_LAW_GRASS and reconstruction 0; g is used; each member's A_g and
+ * m_g replace p's).  stream: hipStream_t for all work (may be NULL).
+ * Returns SVE_ERR_ARG for invalid members (size, h <= 0, m_g outside
+ * [1, 4]) or parameters.
  */
 int sve_ens_create(sve_ens **ens, int n, const sve_member *members,
                    const sve_params *p, void *stream);

@@ -62,6 +62,7 @@ int sve::validate_params(const sve_params* p, int dim, const sve_bc* bc) {
     if (!p || !bc) return SVE_ERR_ARG;
     if (!(p->g > 0.0) || !std::isfinite(p->g)) return SVE_ERR_ARG;
     if (p->law < SVE_LAW_GRASS || p->law > SVE_LAW_CAMENEN) return SVE_ERR_ARG;
+    if (p->reconstruction != 0 && p->reconstruction != 1) return SVE_ERR_ARG;
     if (p->law == SVE_LAW_GRASS) {
         if (!(p->m_g >= 1.0 && p->m_g <= 4.0)) return SVE_ERR_ARG;
         if (!std::isfinite(p->A_g)) return SVE_ERR_ARG;
@@ -91,6 +92,7 @@ Model sve::make_model(int nx, int ny, double Lx, double Ly, int dim, const sve_p
     M.law = p->law;
     M.friction = p->friction;
     M.momentum_friction = p->momentum_friction ? 1 : 0;
+    M.wb = p->reconstruction ? 1 : 0;
     M.mg_is3 = (p->m_g == 3.0);
     M.mg_is1 = (p->m_g == 1.0);
     M.nx = nx;
@@ -146,11 +148,16 @@ void launch_update(sve_ctx* c, int src, int dst, int n, double cfl, double t_end
     const long long N = (long long)M.nx * M.ny;
     const unsigned blocks = (unsigned)((N + UPDATE_BLOCK - 1) / UPDATE_BLOCK);
     const int cl = closure_class(M);
-    auto kern = cl == CL_GRASS3 ? k_update<T, CL_GRASS3>
-              : cl == CL_GRASS1 ? k_update<T, CL_GRASS1>
-              : cl == CL_GRASSM ? k_update<T, CL_GRASSM>
-              : cl == CL_MPM    ? k_update<T, CL_MPM>
-                                : k_update<T, CL_THRESH>;
+    auto kern = M.wb ? (cl == CL_GRASS3 ? k_update<T, CL_GRASS3, true>
+                      : cl == CL_GRASS1 ? k_update<T, CL_GRASS1, true>
+                      : cl == CL_GRASSM ? k_update<T, CL_GRASSM, true>
+                      : cl == CL_MPM    ? k_update<T, CL_MPM, true>
+                                        : k_update<T, CL_THRESH, true>)
+                     : (cl == CL_GRASS3 ? k_update<T, CL_GRASS3, false>
+                      : cl == CL_GRASS1 ? k_update<T, CL_GRASS1, false>
+                      : cl == CL_GRASSM ? k_update<T, CL_GRASSM, false>
+                      : cl == CL_MPM    ? k_update<T, CL_MPM, false>
+                                        : k_update<T, CL_THRESH, false>);
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(UPDATE_BLOCK), 0, c->stream, M,
                        view_of<T>(c, src), view_of<T>(c, dst), (const double*)c->Ag, c->ctrl,
                        n, cfl, t_end, fixed_dt);
@@ -172,7 +179,9 @@ StateView<double> rview(sve_ctx* c, int b) {
 template <typename T>
 int run_steps(sve_ctx* c, int n, double cfl, double t_end, double fixed_dt) {
     const bool cfl_mode = !(fixed_dt > 0.0);
-    const bool resid = cfl_mode && c->path == SVE_PATH_RESIDUAL && c->M.dim == 2;
+    // the well-balanced variant's 2D steps run on the split kernels
+    const bool split_only = c->M.wb && c->M.dim == 2;
+    const bool resid = cfl_mode && c->path == SVE_PATH_RESIDUAL && c->M.dim == 2 && !split_only;
     c->last_resid = resid;
     const int tiles_y = fused_tiles_y(c->M.nx, c->M.ny, c->fused_ty, c->wave_slots);
     if (resid) {
@@ -205,7 +214,7 @@ int run_steps(sve_ctx* c, int n, double cfl, double t_end, double fixed_dt) {
                                        rview(c, dst), c->Ag, c->ctrl, step, cfl, t_end, tiles_y,
                                        c->stream);
             } else if ((c->path == SVE_PATH_FUSED || c->path == SVE_PATH_RESIDUAL) &&
-                       c->M.dim == 2) {
+                       c->M.dim == 2 && !split_only) {
                 launch_fused<T>(c, src, dst, step, cfl, t_end, fixed_dt);
             } else {
                 launch_update<T>(c, src, dst, step, cfl, t_end, fixed_dt);

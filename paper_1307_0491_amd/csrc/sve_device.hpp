@@ -203,6 +203,7 @@ __device__ __forceinline__ double dmin(double a, double b) {
 // Everything a kernel needs about the model and the grid, passed by value.
 struct Model {
     int law, friction, momentum_friction;
+    int wb;               // well-balanced variant (hydrostatic reconstruction)
     int mg_is3, mg_is1;
     int nx, ny;           // ny == 1 with dim == 1 for 1D
     int dim;
@@ -506,6 +507,56 @@ __device__ __forceinline__ unsigned iface_flux(const Side& L, const Side& R, dou
                                                Flux& F) {
     double speed;
     return iface_flux(L, R, g, F, speed);
+}
+
+// ---------------------------------------------------------------------------
+// Well-balanced variant: hydrostatic reconstruction (Audusse, Bouchut,
+// Bristeau, Klein and Perthame, 2004) with the relaxation solver above as
+// the interface solver.  Between cells A (left or below) and B: z* =
+// max(z_A, z_B), h* = max(0, h + z - z*) on each side with the velocities
+// kept; the relaxation problem between the projected reconstructed states
+// on the bed z*; and the hydrostatic corrections g/2 (h^2 - h*^2) added to
+// the momentum flux each cell sees.  A and B are the cells' own projections
+// (only h, u, v and z are read); agA, agB their Grass constants.  NX: the
+// interface normal is x (else y).
+// ---------------------------------------------------------------------------
+struct Recon {
+    Cell A, B;             // projected reconstructed states
+    double corrA, corrB;   // g/2 (h^2 - h*^2) of each side
+};
+
+template <int CL>
+__device__ __forceinline__ Recon reconstruct(const Model& M, const Cell& A, double agA,
+                                             const Cell& B, double agB) {
+    Recon r;
+    const double zs = dmax(A.z, B.z);
+    const double hAs = dmax((A.h + A.z) - zs, 0.0);
+    const double hBs = dmax((B.h + B.z) - zs, 0.0);
+    r.A = project<CL>(M, hAs, hAs * A.u, hAs * A.v, zs, agA);
+    r.B = project<CL>(M, hBs, hBs * B.u, hBs * B.v, zs, agB);
+    r.corrA = 0.5 * M.g * (A.h * A.h - hAs * hAs);
+    r.corrB = 0.5 * M.g * (B.h * B.h - hBs * hBs);
+    return r;
+}
+
+template <int CL, bool NX>
+__device__ __forceinline__ unsigned wb_iface_flux(const Model& M, const Cell& A, double agA,
+                                                  const Cell& B, double agB, Flux& F,
+                                                  double& speed) {
+    const Recon r = reconstruct<CL>(M, A, agA, B, agB);
+    const unsigned e = NX ? iface_flux(side_x(r.A), side_x(r.B), M.g, F, speed)
+                          : iface_flux(side_y(r.A), side_y(r.B), M.g, F, speed);
+    F.FhuL = F.FhuL + r.corrA;
+    F.FhuR = F.FhuR + r.corrB;
+    return e;
+}
+
+template <int CL, bool NX>
+__device__ __forceinline__ double wb_iface_speed(const Model& M, const Cell& A, double agA,
+                                                 const Cell& B, double agB) {
+    const Recon r = reconstruct<CL>(M, A, agA, B, agB);
+    return NX ? iface_speed(side_x(r.A), side_x(r.B), M.g)
+              : iface_speed(side_y(r.A), side_y(r.B), M.g);
 }
 
 // Coefficient phi of the optional semi-implicit momentum friction,

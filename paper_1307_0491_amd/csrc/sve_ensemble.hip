@@ -248,7 +248,7 @@ int sve_ens_create(sve_ens** out, int n, const sve_member* members, const sve_pa
                    void* stream) {
     if (!out || n < 1 || !members || !p) return SVE_ERR_ARG;
     *out = nullptr;
-    if (p->law != SVE_LAW_GRASS || !(p->g > 0.0)) return SVE_ERR_ARG;
+    if (p->law != SVE_LAW_GRASS || !(p->g > 0.0) || p->reconstruction) return SVE_ERR_ARG;
     sve_bc bc[4] = {{SVE_BC_PERIODIC, 0, 0, 0}, {SVE_BC_PERIODIC, 0, 0, 0},
                     {SVE_BC_PERIODIC, 0, 0, 0}, {SVE_BC_PERIODIC, 0, 0, 0}};
     for (int m = 0; m < n; ++m) {
@@ -318,7 +318,7 @@ int sve_ens_create(sve_ens** out, int n, const sve_member* members, const sve_pa
     for (int m = 0; m < n && ok; ++m) {
         const EnsMember& E = e->mem[m];
         const long long nint = (long long)(E.M.nx + 1) * E.M.ny + (long long)E.M.nx * (E.M.ny + 1);
-        hipLaunchKernelGGL((k_speeds<double, CL_GRASSM>), dim3((unsigned)((nint + 255) / 256)),
+        hipLaunchKernelGGL((k_speeds<double, CL_GRASSM, false>), dim3((unsigned)((nint + 255) / 256)),
                            dim3(SPEED_BLOCK), 0, e->stream, E.M, view(E.buf[0], E.pitch),
                            (const double*)nullptr, E.ctrl, 0);
     }

@@ -38,7 +38,7 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
     return r;
 }
 
-template <typename T, int CL>
+template <typename T, int CL, bool WB>
 __global__ void __launch_bounds__(SPEED_BLOCK)
 k_speeds(Model M, StateView<T> S, const double* __restrict__ Agf, Ctrl* ctrl, int slot) {
     __shared__ double sh[2][SPEED_BLOCK / 64];
@@ -49,21 +49,23 @@ k_speeds(Model M, StateView<T> S, const double* __restrict__ Agf, Ctrl* ctrl, in
     double sx = 0.0, sy = 0.0;
     if (t < nxi) {
         const int j = (int)(t / (M.nx + 1)), m = (int)(t % (M.nx + 1));
-        double h, hu, hv, z, ag;
-        fetch(M, S, Agf, m - 1, j, h, hu, hv, z, ag);
-        const Cell L = project<CL>(M, h, hu, hv, z, ag);
-        fetch(M, S, Agf, m, j, h, hu, hv, z, ag);
-        const Cell R = project<CL>(M, h, hu, hv, z, ag);
-        sx = iface_speed(side_x(L), side_x(R), M.g);
+        double h, hu, hv, z, agL, agR;
+        fetch(M, S, Agf, m - 1, j, h, hu, hv, z, agL);
+        const Cell L = project<CL>(M, h, hu, hv, z, agL);
+        fetch(M, S, Agf, m, j, h, hu, hv, z, agR);
+        const Cell R = project<CL>(M, h, hu, hv, z, agR);
+        sx = WB ? wb_iface_speed<CL, true>(M, L, agL, R, agR)
+                : iface_speed(side_x(L), side_x(R), M.g);
     } else if (t < nxi + nyi) {
         const long long u = t - nxi;
         const int i = (int)(u % M.nx), m = (int)(u / M.nx);
-        double h, hu, hv, z, ag;
-        fetch(M, S, Agf, i, m - 1, h, hu, hv, z, ag);
-        const Cell L = project<CL>(M, h, hu, hv, z, ag);
-        fetch(M, S, Agf, i, m, h, hu, hv, z, ag);
-        const Cell R = project<CL>(M, h, hu, hv, z, ag);
-        sy = iface_speed(side_y(L), side_y(R), M.g);
+        double h, hu, hv, z, agL, agR;
+        fetch(M, S, Agf, i, m - 1, h, hu, hv, z, agL);
+        const Cell L = project<CL>(M, h, hu, hv, z, agL);
+        fetch(M, S, Agf, i, m, h, hu, hv, z, agR);
+        const Cell R = project<CL>(M, h, hu, hv, z, agR);
+        sy = WB ? wb_iface_speed<CL, false>(M, L, agL, R, agR)
+                : iface_speed(side_y(L), side_y(R), M.g);
     }
     const double bx = block_max<SPEED_BLOCK>(sx, sh[0]);
     const double by = block_max<SPEED_BLOCK>(sy, sh[1]);
@@ -81,11 +83,16 @@ void launch_speeds_model(const Model& M, StateView<T> S, const double* Ag, Ctrl*
                            (M.dim == 2 ? (long long)M.nx * (M.ny + 1) : 0);
     const unsigned blocks = (unsigned)((nint + SPEED_BLOCK - 1) / SPEED_BLOCK);
     const int cl = closure_class(M);
-    auto kern = cl == CL_GRASS3 ? k_speeds<T, CL_GRASS3>
-              : cl == CL_GRASS1 ? k_speeds<T, CL_GRASS1>
-              : cl == CL_GRASSM ? k_speeds<T, CL_GRASSM>
-              : cl == CL_MPM    ? k_speeds<T, CL_MPM>
-                                : k_speeds<T, CL_THRESH>;
+    auto kern = M.wb ? (cl == CL_GRASS3 ? k_speeds<T, CL_GRASS3, true>
+                      : cl == CL_GRASS1 ? k_speeds<T, CL_GRASS1, true>
+                      : cl == CL_GRASSM ? k_speeds<T, CL_GRASSM, true>
+                      : cl == CL_MPM    ? k_speeds<T, CL_MPM, true>
+                                        : k_speeds<T, CL_THRESH, true>)
+                     : (cl == CL_GRASS3 ? k_speeds<T, CL_GRASS3, false>
+                      : cl == CL_GRASS1 ? k_speeds<T, CL_GRASS1, false>
+                      : cl == CL_GRASSM ? k_speeds<T, CL_GRASSM, false>
+                      : cl == CL_MPM    ? k_speeds<T, CL_MPM, false>
+                                        : k_speeds<T, CL_THRESH, false>);
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(SPEED_BLOCK), 0, stream, M, S, Ag, ctrl, slot);
 }
 
@@ -124,7 +131,18 @@ __device__ __forceinline__ void apply_friction(const Model& M, double dt, double
     hv = hv / den;
 }
 
-template <typename T, int CL>
+// Interface flux between projected cells A and B (A left of or below B):
+// the relaxation solve, or that of the hydrostatic reconstruction (WB).
+template <int CL, bool WB, bool NX>
+__device__ __forceinline__ unsigned cell_flux(const Model& M, const Cell& A, double agA,
+                                              const Cell& B, double agB, Flux& F) {
+    double sp;
+    if (WB) return wb_iface_flux<CL, NX>(M, A, agA, B, agB, F, sp);
+    return NX ? iface_flux(side_x(A), side_x(B), M.g, F, sp)
+              : iface_flux(side_y(A), side_y(B), M.g, F, sp);
+}
+
+template <typename T, int CL, bool WB>
 __global__ void __launch_bounds__(UPDATE_BLOCK)
 k_update(Model M, StateView<T> S, StateView<T> D, const double* __restrict__ Agf, Ctrl* ctrl,
          int n, double cfl, double t_end, double fixed_dt) {
@@ -135,26 +153,27 @@ k_update(Model M, StateView<T> S, StateView<T> D, const double* __restrict__ Agf
     const long long k = (long long)blockIdx.x * UPDATE_BLOCK + threadIdx.x;
     if (k >= N) return;
     const int i = (int)(k % M.nx), j = (int)(k / M.nx);
-    double h, hu, hv, z, ag;
-    fetch(M, S, Agf, i, j, h, hu, hv, z, ag);
-    const Cell C = project<CL>(M, h, hu, hv, z, ag);
-    fetch(M, S, Agf, i - 1, j, h, hu, hv, z, ag);
-    const Cell W = project<CL>(M, h, hu, hv, z, ag);
-    fetch(M, S, Agf, i + 1, j, h, hu, hv, z, ag);
-    const Cell E = project<CL>(M, h, hu, hv, z, ag);
+    double h, hu, hv, z, agC, agW, agE;
+    fetch(M, S, Agf, i, j, h, hu, hv, z, agC);
+    const Cell C = project<CL>(M, h, hu, hv, z, agC);
+    fetch(M, S, Agf, i - 1, j, h, hu, hv, z, agW);
+    const Cell W = project<CL>(M, h, hu, hv, z, agW);
+    fetch(M, S, Agf, i + 1, j, h, hu, hv, z, agE);
+    const Cell E = project<CL>(M, h, hu, hv, z, agE);
     Flux fl, fr;
-    unsigned err = iface_flux(side_x(W), side_x(C), M.g, fl);
-    err |= iface_flux(side_x(C), side_x(E), M.g, fr);
+    unsigned err = cell_flux<CL, WB, true>(M, W, agW, C, agC, fl);
+    err |= cell_flux<CL, WB, true>(M, C, agC, E, agE, fr);
     const double lx = st.dt / M.dx;
     double hn, hun, hvn, zn;
     if (M.dim == 2) {
-        fetch(M, S, Agf, i, j - 1, h, hu, hv, z, ag);
-        const Cell So = project<CL>(M, h, hu, hv, z, ag);
-        fetch(M, S, Agf, i, j + 1, h, hu, hv, z, ag);
-        const Cell No = project<CL>(M, h, hu, hv, z, ag);
+        double agS, agN;
+        fetch(M, S, Agf, i, j - 1, h, hu, hv, z, agS);
+        const Cell So = project<CL>(M, h, hu, hv, z, agS);
+        fetch(M, S, Agf, i, j + 1, h, hu, hv, z, agN);
+        const Cell No = project<CL>(M, h, hu, hv, z, agN);
         Flux gb, gt;
-        err |= iface_flux(side_y(So), side_y(C), M.g, gb);
-        err |= iface_flux(side_y(C), side_y(No), M.g, gt);
+        err |= cell_flux<CL, WB, false>(M, So, agS, C, agC, gb);
+        err |= cell_flux<CL, WB, false>(M, C, agC, No, agN, gt);
         const double ly = st.dt / M.dy;
         hn = C.h - lx * (fr.Fh - fl.Fh) - ly * (gt.Fh - gb.Fh);
         hun = C.hu - lx * (fr.FhuL - fl.FhuR) - ly * (gt.Fht - gb.Fht);

@@ -63,17 +63,18 @@ __device__ __forceinline__ void res_cell(const Model& M, const ResLds& L,
     if (g >= 0 && M.bc_kind[g] == BC_INFLOW) { h = M.bc_h[g]; hu = M.bc_hu[g]; }
 }
 
-template <int CL>
+template <int CL, bool WB>
 __device__ __forceinline__ double res_max_speed(const Model& M, const ResLds& L,
                                                 const double* __restrict__ Agf) {
     double s = 0.0;
     for (int m = threadIdx.x; m <= M.nx; m += RES_BLOCK) {
-        double h, hu, z, ag;
-        res_cell(M, L, Agf, m - 1, h, hu, z, ag);
-        const Cell A = project<CL>(M, h, hu, 0.0, z, ag);
-        res_cell(M, L, Agf, m, h, hu, z, ag);
-        const Cell B = project<CL>(M, h, hu, 0.0, z, ag);
-        s = fmax(s, iface_speed(side_x(A), side_x(B), M.g));
+        double h, hu, z, agA, agB;
+        res_cell(M, L, Agf, m - 1, h, hu, z, agA);
+        const Cell A = project<CL>(M, h, hu, 0.0, z, agA);
+        res_cell(M, L, Agf, m, h, hu, z, agB);
+        const Cell B = project<CL>(M, h, hu, 0.0, z, agB);
+        s = fmax(s, WB ? wb_iface_speed<CL, true>(M, A, agA, B, agB)
+                       : iface_speed(side_x(A), side_x(B), M.g));
     }
     s = wave_max(s);
     if ((threadIdx.x & 63) == 0) L.red[threadIdx.x >> 6] = s;
@@ -84,7 +85,7 @@ __device__ __forceinline__ double res_max_speed(const Model& M, const ResLds& L,
     return r;
 }
 
-template <typename T, int CL>
+template <typename T, int CL, bool WB>
 __global__ void __launch_bounds__(RES_BLOCK)
 k_resident_1d(Model M, StateView<T> S, StateView<T> D, const double* __restrict__ Agf,
               Ctrl* ctrl, int n0, int nsteps, double cfl, double t_end, double fixed_dt) {
@@ -116,14 +117,15 @@ k_resident_1d(Model M, StateView<T> S, StateView<T> D, const double* __restrict_
         unsigned e = 0u;
         double s = 0.0;
         for (int m = threadIdx.x; m <= nx; m += RES_BLOCK) {
-            double h, hu, z, ag;
-            res_cell(M, L, Agf, m - 1, h, hu, z, ag);
-            const Cell A = project<CL>(M, h, hu, 0.0, z, ag);
-            res_cell(M, L, Agf, m, h, hu, z, ag);
-            const Cell B = project<CL>(M, h, hu, 0.0, z, ag);
+            double h, hu, z, agA, agB;
+            res_cell(M, L, Agf, m - 1, h, hu, z, agA);
+            const Cell A = project<CL>(M, h, hu, 0.0, z, agA);
+            res_cell(M, L, Agf, m, h, hu, z, agB);
+            const Cell B = project<CL>(M, h, hu, 0.0, z, agB);
             Flux F;
             double sp;
-            e |= iface_flux(side_x(A), side_x(B), M.g, F, sp);
+            e |= WB ? wb_iface_flux<CL, true>(M, A, agA, B, agB, F, sp)
+                    : iface_flux(side_x(A), side_x(B), M.g, F, sp);
             s = dmax(s, sp);
             L.Fh[m] = F.Fh;
             L.FL[m] = F.FhuL;
@@ -195,7 +197,7 @@ k_resident_1d(Model M, StateView<T> S, StateView<T> D, const double* __restrict_
         S_known = false;
     }
     // outer wave speed of the state left in LDS, for the next call's first step
-    if (cfl_mode && !S_known) S_cur = res_max_speed<CL>(M, L, Agf);
+    if (cfl_mode && !S_known) S_cur = res_max_speed<CL, WB>(M, L, Agf);
     // write back the last good state into the buffer the host expects
     const StateView<T>& out = (done & 1) ? D : S;
     for (int i = threadIdx.x; i < nx; i += RES_BLOCK) {
@@ -239,11 +241,17 @@ void launch_resident(sve_ctx* c, int n, double cfl, double t_end, double fixed_d
     D = StateView<T>{b1, b1 + c->pitch, b1 + 2 * c->pitch, b1 + 3 * c->pitch};
     const size_t lds = res_lds_bytes(c->M.nx);
     const int cl = closure_class(c->M);
-    auto kern = cl == CL_GRASS3 ? k_resident_1d<T, CL_GRASS3>
-              : cl == CL_GRASS1 ? k_resident_1d<T, CL_GRASS1>
-              : cl == CL_GRASSM ? k_resident_1d<T, CL_GRASSM>
-              : cl == CL_MPM    ? k_resident_1d<T, CL_MPM>
-                                : k_resident_1d<T, CL_THRESH>;
+    const bool wb = c->M.wb;
+    auto kern = wb ? (cl == CL_GRASS3 ? k_resident_1d<T, CL_GRASS3, true>
+                    : cl == CL_GRASS1 ? k_resident_1d<T, CL_GRASS1, true>
+                    : cl == CL_GRASSM ? k_resident_1d<T, CL_GRASSM, true>
+                    : cl == CL_MPM    ? k_resident_1d<T, CL_MPM, true>
+                                      : k_resident_1d<T, CL_THRESH, true>)
+                   : (cl == CL_GRASS3 ? k_resident_1d<T, CL_GRASS3, false>
+                    : cl == CL_GRASS1 ? k_resident_1d<T, CL_GRASS1, false>
+                    : cl == CL_GRASSM ? k_resident_1d<T, CL_GRASSM, false>
+                    : cl == CL_MPM    ? k_resident_1d<T, CL_MPM, false>
+                                      : k_resident_1d<T, CL_THRESH, false>);
     hipLaunchKernelGGL(kern, dim3(1), dim3(RES_BLOCK), lds, c->stream,
                        c->M, S, D, (const double*)c->Ag, c->ctrl, (int)c->nsteps, n, cfl, t_end,
                        fixed_dt);

@@ -28,11 +28,12 @@ class Params:
     s: float = 2.65
     tau_cr: float = 0.05
     momentum_friction: int = 0
+    reconstruction: int = 0
 
     def to_c(self) -> _lib.SveParams:
         return _lib.SveParams(self.law, self.g, self.A_g, self.m_g, self.friction,
                               self.fric_coef, self.d_s, self.s, self.tau_cr,
-                              self.momentum_friction)
+                              self.momentum_friction, self.reconstruction)
 
 
 @dataclasses.dataclass

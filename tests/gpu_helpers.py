@@ -19,7 +19,8 @@ def rel_linf(a, b):
 def to_oracle_params(p):
     return O.Params(law=p.law, g=p.g, A_g=p.A_g, m_g=p.m_g, friction=p.friction,
                     fric_coef=p.fric_coef, d_s=p.d_s, s=p.s, tau_cr=p.tau_cr,
-                    momentum_friction=p.momentum_friction)
+                    momentum_friction=p.momentum_friction,
+                    reconstruction=p.reconstruction)
 
 
 def to_oracle_bcs(bcs):
