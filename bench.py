@@ -327,6 +327,41 @@ def paper2d_leg(args, sve, torch):
     return out
 
 
+def wb_leg(args, sve, torch):
+    """The well-balanced variant (hydrostatic reconstruction) against the
+    paper's scheme on the paper's 2D bump at 2000 x 2000 cells (inflow (9.9,
+    10, 0) west, free elsewhere, Grass A_g = 0.1, m_g = 3, CFL 0.5, FP64),
+    both on the default (fused) path."""
+    import workloads as W
+    n = 2000
+    h, hu, hv, zb, dx, dy = W.dune2d(n, n, base=0.1)
+    bcs = [sve.BC(sve.BC_INFLOW, 9.9, 10.0, 0.0), sve.BC(sve.BC_FREE), sve.BC(sve.BC_FREE),
+           sve.BC(sve.BC_FREE)]
+    out = {"nx": n, "ny": n, "steps": args.wb_steps}
+    for name, rec in (("paper_scheme", 0), ("well_balanced", 1)):
+        p = sve.Params(law=sve.LAW_GRASS, A_g=0.1, m_g=3.0, reconstruction=rec)
+        s = sve.Solver(h, hu, zb, hv, lx=1000.0, ly=1000.0, params=p, bcs=bcs,
+                       stream=sve.current_stream_handle())
+        s.step(20, 0.5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(args.wb_steps, 0.5)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        per_launch = s.last_elapsed_ms() * 1e-3 / args.wb_steps
+        (gh, _, _, _), t, _, _ = s.get_state()
+        s.close()
+        out[name] = {"cell_updates_per_s": n * n * args.wb_steps / wall,
+                     "ms_per_step": wall * 1e3 / args.wb_steps,
+                     "avg_launch_us": per_launch * 1e6,
+                     "hbm_frac": BYTES_PER_CELL_FP64 * n * n / per_launch / 1e9 / HBM_PEAK_GBS,
+                     "sim_time_s": t, "finite": bool(np.all(np.isfinite(gh)) and np.all(gh > 0))}
+        progress(f"wb {name}: {args.wb_steps} steps in {wall:.3f} s")
+    out["cost_vs_paper_scheme"] = (out["well_balanced"]["avg_launch_us"]
+                                   / out["paper_scheme"]["avg_launch_us"])
+    return out
+
+
 def ensemble_leg(args, sve, torch):
     import workloads as W
     from paper_1307_0491_amd.ensemble import Ensemble
@@ -454,9 +489,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--cpu-1d-steps", type=int, default=20000)
-    ap.add_argument("--legs", default="main,mpm,dune1d,ensemble,adjoint,paper2d",
-                    help="comma list of main, mpm, dune1d, ensemble, adjoint, paper2d "
-                         "(paper2d: the paper's 4000x4000 bump to T)")
+    ap.add_argument("--legs", default="main,mpm,dune1d,ensemble,adjoint,paper2d,wb",
+                    help="comma list of main, mpm, dune1d, ensemble, adjoint, paper2d, wb "
+                         "(paper2d: the paper's 4000x4000 bump to T; wb: the well-balanced "
+                         "variant against the paper's scheme)")
+    ap.add_argument("--wb-steps", type=int, default=1000)
     ap.add_argument("--paper-n", type=int, default=4000)
     ap.add_argument("--paper-runs", default="scaling", choices=["scaling", "both"],
                     help="scaling: A_g = 0.1 to T = 1000 s (the run of the paper's "
@@ -503,6 +540,8 @@ def main():
         out["adjoint"] = adjoint_leg(args, sve, torch)
     if "paper2d" in legs:
         out["paper2d"] = paper2d_leg(args, sve, torch)
+    if "wb" in legs:
+        out["wb"] = wb_leg(args, sve, torch)
     # the main leg runs after the others, on a device at its working clock
     if "main" in legs:
         wall, kern_ms, t, ns, ok = main_leg(args, sve, torch)

@@ -101,8 +101,9 @@ typedef struct sve_params {
  * the bed z*, and each cell's momentum flux gets g/2 (h^2 - h*^2).  A lake at
  * rest then stays at rest for every bedload law and exponent; on a flat bed
  * the variant is the paper's scheme.  Supported by sve_step and
- * sve_step_fixed_dt on every path (2D steps run on the split kernels); the
- * adjoint, the ensemble and sve_step_dev_noalloc return SVE_ERR_ARG for it.
+ * sve_step_fixed_dt on the fused, split and 1D resident paths (the residual
+ * path runs it as fused); the adjoint, the ensemble and
+ * sve_step_dev_noalloc return SVE_ERR_ARG for it.
  */
 
 typedef struct sve_bc {

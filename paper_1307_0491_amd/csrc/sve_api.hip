@@ -166,9 +166,13 @@ void launch_update(sve_ctx* c, int src, int dst, int n, double cfl, double t_end
 template <typename T>
 void launch_fused(sve_ctx* c, int src, int dst, int n, double cfl, double t_end,
                   double fixed_dt) {
-    launch_fused_rows<T>(c->M, view_of<T>(c, src), view_of<T>(c, dst), c->Ag, c->ctrl, n, cfl,
-                         t_end, fixed_dt,
-                         fused_tiles_y(c->M.nx, c->M.ny, c->fused_ty, c->wave_slots), c->stream);
+    const int tiles_y = fused_tiles_y(c->M.nx, c->M.ny, c->fused_ty, c->wave_slots);
+    if (c->M.wb)
+        launch_fused_rows<T, true>(c->M, view_of<T>(c, src), view_of<T>(c, dst), c->Ag, c->ctrl,
+                                   n, cfl, t_end, fixed_dt, tiles_y, c->stream);
+    else
+        launch_fused_rows<T>(c->M, view_of<T>(c, src), view_of<T>(c, dst), c->Ag, c->ctrl, n,
+                             cfl, t_end, fixed_dt, tiles_y, c->stream);
 }
 
 StateView<double> rview(sve_ctx* c, int b) {
@@ -179,9 +183,8 @@ StateView<double> rview(sve_ctx* c, int b) {
 template <typename T>
 int run_steps(sve_ctx* c, int n, double cfl, double t_end, double fixed_dt) {
     const bool cfl_mode = !(fixed_dt > 0.0);
-    // the well-balanced variant's 2D steps run on the split kernels
-    const bool split_only = c->M.wb && c->M.dim == 2;
-    const bool resid = cfl_mode && c->path == SVE_PATH_RESIDUAL && c->M.dim == 2 && !split_only;
+    // the residual path has no well-balanced variant: its steps run fused
+    const bool resid = cfl_mode && c->path == SVE_PATH_RESIDUAL && c->M.dim == 2 && !c->M.wb;
     c->last_resid = resid;
     const int tiles_y = fused_tiles_y(c->M.nx, c->M.ny, c->fused_ty, c->wave_slots);
     if (resid) {
@@ -214,7 +217,7 @@ int run_steps(sve_ctx* c, int n, double cfl, double t_end, double fixed_dt) {
                                        rview(c, dst), c->Ag, c->ctrl, step, cfl, t_end, tiles_y,
                                        c->stream);
             } else if ((c->path == SVE_PATH_FUSED || c->path == SVE_PATH_RESIDUAL) &&
-                       c->M.dim == 2 && !split_only) {
+                       c->M.dim == 2) {
                 launch_fused<T>(c, src, dst, step, cfl, t_end, fixed_dt);
             } else {
                 launch_update<T>(c, src, dst, step, cfl, t_end, fixed_dt);

@@ -235,6 +235,25 @@ __device__ __forceinline__ Side ghost_side_y(const Model& M, int side, const Sid
     return side_y(project<CL>(M, M.bc_h[side], M.bc_hu[side], M.bc_hv[side], c.z, ag));
 }
 
+// Projected ghost cell next to a cell `c` for the well-balanced variant
+// (FREE: the cell itself; INFLOW: the Dirichlet (h, hu, hv) with the cell's
+// bed and A_g).
+template <int CL>
+__device__ __forceinline__ Cell ghost_cell(const Model& M, int side, const Cell& c, double ag) {
+    if (M.bc_kind[side] != BC_INFLOW) return c;
+    return project<CL>(M, M.bc_h[side], M.bc_hu[side], M.bc_hv[side], c.z, ag);
+}
+
+// The next lane's h, u, v, z (what the well-balanced interface reads).
+__device__ __forceinline__ Cell next_cell(const Cell& c) {
+    Cell n;
+    n.h = dpp<DPP_NEXT>(c.h);
+    n.u = dpp<DPP_NEXT>(c.u);
+    n.v = dpp<DPP_NEXT>(c.v);
+    n.z = dpp<DPP_NEXT>(c.z);
+    return n;
+}
+
 // Per-lane state carried from one row to the next.
 struct RowCarry {
     double h, tau, u, v, Pi, z, qy, by2, inv, hu, hv, ag;       // projected row r-1
@@ -242,6 +261,8 @@ struct RowCarry {
     unsigned eX, eY;
     double Yh, Yt, YR, Yz;                                     // y-flux below row r-1
     Side N;                                                    // y view, new state of row r-2
+    Cell NC;                                                   // the same cell (well-balanced)
+    double Nag;                                                // its A_g (well-balanced)
     // new state of the row updated last, stored at the start of the next
     // row: a store issued just before the loop's wait for the next row's
     // loads would hold the wavefront until the write completes
@@ -255,7 +276,7 @@ struct RowCarry {
 // The step's dt follows from the control block (cfl, t_end, fixed_dt as for
 // step_time); exactly one tile of the grid passes bookkeep = true and
 // records the step.  All arguments must be wave-uniform.
-template <typename T, int CL, bool SPEEDS>
+template <typename T, int CL, bool SPEEDS, bool WB = false>
 __device__ __forceinline__ void fused_tile(const Model& M, const StateView<T>& S,
                                            const StateView<T>& D, const double* __restrict__ Agf,
                                            Ctrl* ctrl, int n, double cfl, double t_end,
@@ -300,7 +321,14 @@ __device__ __forceinline__ void fused_tile(const Model& M, const StateView<T>& S
         unsigned eXn = 0;
         if (do_x.value) {
             Flux X;
-            const unsigned e = iface_flux(side_x(P), next_side_x(P), M.g, X);
+            unsigned e;
+            if constexpr (WB) {
+                double sp;
+                e = wb_iface_flux<CL, true>(M, P, cur.ag, next_cell(P), dpp<DPP_NEXT>(cur.ag), X,
+                                            sp);
+            } else {
+                e = iface_flux(side_x(P), next_side_x(P), M.g, X);
+            }
             dXh = X.Fh - dpp<DPP_PREV>(X.Fh);
             dXm = X.FhuL - dpp<DPP_PREV>(X.FhuR);
             dXt = X.Fht - dpp<DPP_PREV>(X.Fht);
@@ -308,8 +336,19 @@ __device__ __forceinline__ void fused_tile(const Model& M, const StateView<T>& S
             eXn = e | dpp_u<DPP_PREV>(e);
         }
         Flux Y;
-        const Side Ls{c.h, c.tau, c.v, c.u, c.Pi, c.z, c.qy, c.by2, c.inv};
-        const unsigned eY = iface_flux(Ls, side_y(P), M.g, Y);
+        unsigned eY;
+        if constexpr (WB) {
+            Cell Lc;
+            Lc.h = c.h;
+            Lc.u = c.u;
+            Lc.v = c.v;
+            Lc.z = c.z;
+            double sp;
+            eY = wb_iface_flux<CL, false>(M, Lc, c.ag, P, cur.ag, Y, sp);
+        } else {
+            const Side Ls{c.h, c.tau, c.v, c.u, c.Pi, c.z, c.qy, c.by2, c.inv};
+            eY = iface_flux(Ls, side_y(P), M.g, Y);
+        }
         if (do_upd.value) {
             const int ru = r - 1;
             double hn = c.h - lx * c.dXh - ly * (Y.Fh - c.Yh);
@@ -349,6 +388,29 @@ __device__ __forceinline__ void fused_tile(const Model& M, const StateView<T>& S
                         ghost_from(M, BCW, hn, hun, hvn);
                     }
                 }
+                if constexpr (WB) {
+                    Cell NY;
+                    if (ring.value && yghost_n) {    // north ghost row of the new state
+                        NY = ghost_cell<CL>(M, BCN, c.NC, c.ag);
+                    } else {
+                        NY = project<CL>(M, hn, hun, hvn, zn, c.ag);
+                        if (!ring.value) {
+                            const double s = wb_iface_speed<CL, true>(M, NY, c.ag, next_cell(NY),
+                                                                      dpp<DPP_NEXT>(c.ag));
+                            if (owned_lane || (lane == 0 && xghost_w)) sx = dmax(sx, s);
+                        }
+                    }
+                    if (!first_upd.value) {
+                        const double s = wb_iface_speed<CL, false>(M, c.NC, c.Nag, NY, c.ag);
+                        if (owned_lane) sy = dmax(sy, s);
+                    } else if (yghost_s) {
+                        const double s = wb_iface_speed<CL, false>(
+                            M, ghost_cell<CL>(M, BCS, NY, c.ag), c.ag, NY, c.ag);
+                        if (owned_lane) sy = dmax(sy, s);
+                    }
+                    c.NC = NY;
+                    c.Nag = c.ag;
+                } else {
                 Side Ny;
                 if (ring.value && yghost_n) {        // north ghost row of the new state
                     Ny = ghost_side_y<CL>(M, BCN, c.N, c.ag);
@@ -370,6 +432,7 @@ __device__ __forceinline__ void fused_tile(const Model& M, const StateView<T>& S
                     if (owned_lane) sy = dmax(sy, s);
                 }
                 c.N = Ny;
+                }
             }
         }
         c.h = P.h; c.tau = P.tau; c.u = P.u; c.v = P.v; c.Pi = P.Pi; c.z = P.z; c.qy = P.qy;
@@ -436,7 +499,7 @@ __device__ __forceinline__ void fused_tile(const Model& M, const StateView<T>& S
 
 // One wavefront per workgroup: workgroup id runs tile xcd_tile(id) of the
 // tiles_x x tiles_y split (row-major; rows by tile_rows).
-template <typename T, int CL, bool SPEEDS>
+template <typename T, int CL, bool SPEEDS, bool WB>
 __global__ void __launch_bounds__(64, FUSED_WAVES_PER_SIMD)
 k_fused(Model M, StateView<T> S, StateView<T> D, const double* __restrict__ Agf, Ctrl* ctrl,
         int n, double cfl, double t_end, double fixed_dt, int tiles_y) {
@@ -444,12 +507,13 @@ k_fused(Model M, StateView<T> S, StateView<T> D, const double* __restrict__ Agf,
     const int t = xcd_tile(blockIdx.x, tiles_x * tiles_y);
     int j0, jend;
     tile_rows(M.ny, tiles_y, t / tiles_x, j0, jend);
-    fused_tile<T, CL, SPEEDS>(M, S, D, Agf, ctrl, n, cfl, t_end, fixed_dt, blockIdx.x == 0,
-                              t % tiles_x, j0, jend);
+    fused_tile<T, CL, SPEEDS, WB>(M, S, D, Agf, ctrl, n, cfl, t_end, fixed_dt, blockIdx.x == 0,
+                                  t % tiles_x, j0, jend);
 }
 
-// tiles_y: number of row tiles (fused_tiles_y), 1 <= tiles_y <= ny.
-template <typename T>
+// tiles_y: number of row tiles (fused_tiles_y), 1 <= tiles_y <= ny.  WB:
+// the well-balanced variant's kernels (M.wb set).
+template <typename T, bool WB = false>
 void launch_fused_rows(const Model& M, StateView<T> S, StateView<T> D, const double* Ag,
                        Ctrl* ctrl, int n, double cfl, double t_end, double fixed_dt, int tiles_y,
                        hipStream_t stream) {
@@ -457,11 +521,12 @@ void launch_fused_rows(const Model& M, StateView<T> S, StateView<T> D, const dou
     const dim3 grid(tiles_x * tiles_y);
     const int cl = closure_class(M);
     const bool sp = !(fixed_dt > 0.0);
-    auto kern = cl == CL_GRASS3 ? (sp ? k_fused<T, CL_GRASS3, true> : k_fused<T, CL_GRASS3, false>)
-              : cl == CL_GRASS1 ? (sp ? k_fused<T, CL_GRASS1, true> : k_fused<T, CL_GRASS1, false>)
-              : cl == CL_GRASSM ? (sp ? k_fused<T, CL_GRASSM, true> : k_fused<T, CL_GRASSM, false>)
-              : cl == CL_MPM    ? (sp ? k_fused<T, CL_MPM, true> : k_fused<T, CL_MPM, false>)
-                                : (sp ? k_fused<T, CL_THRESH, true> : k_fused<T, CL_THRESH, false>);
+    constexpr bool W = WB;
+    auto kern = cl == CL_GRASS3 ? (sp ? k_fused<T, CL_GRASS3, true, W> : k_fused<T, CL_GRASS3, false, W>)
+              : cl == CL_GRASS1 ? (sp ? k_fused<T, CL_GRASS1, true, W> : k_fused<T, CL_GRASS1, false, W>)
+              : cl == CL_GRASSM ? (sp ? k_fused<T, CL_GRASSM, true, W> : k_fused<T, CL_GRASSM, false, W>)
+              : cl == CL_MPM    ? (sp ? k_fused<T, CL_MPM, true, W> : k_fused<T, CL_MPM, false, W>)
+                                : (sp ? k_fused<T, CL_THRESH, true, W> : k_fused<T, CL_THRESH, false, W>);
     hipLaunchKernelGGL(kern, grid, dim3(64), 0, stream, M, S, D, Ag, ctrl, n, cfl, t_end,
                        fixed_dt, tiles_y);
 }
