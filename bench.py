@@ -46,8 +46,8 @@ NX = NY = 2000
 # WRITE_SIZE x 1.0000.  Valid only for the kernel sources it was taken on
 # (kernel_source_hash) and the automatic tile split; otherwise the bench
 # reports null.  Summary: profiles/k_fused_dune2000_fp64_hbm_traffic.md.
-TRAFFIC = {"src": "5ef6c1a3c2b1c12f", "rows": 0,
-           "fetch_kib": 69020.2, "write_kib": 125207.9,
+TRAFFIC = {"src": "ce47129ea1bbf1e2", "rows": 0,
+           "fetch_kib": 69021.0, "write_kib": 125206.5,
            "bytes_per_launch": 269.56e6}
 
 # VALU activity of the same kernel, build and workload (rocprofv3 --pmc
@@ -55,7 +55,7 @@ TRAFFIC = {"src": "5ef6c1a3c2b1c12f", "rows": 0,
 # dispatch, summed over the device).  The chip issues one wave64 VALU
 # instruction per SIMD every 4 cycles (16 for FP64 transcendentals):
 # 256 CUs x 4 SIMDs at 2.4 GHz.  Summary: profiles/k_fused_dune2000_fp64_valu.md.
-VALU = {"src": "5ef6c1a3c2b1c12f", "rows": 0,
+VALU = {"src": "ce47129ea1bbf1e2", "rows": 0,
         "insts_valu": 39035198, "insts_trans_f64": 1111242}
 SIMDS = 256 * 4
 CLOCK_HZ = 2.4e9
