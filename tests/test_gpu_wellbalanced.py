@@ -80,6 +80,35 @@ def test_paper_bump(sve, Ag, mg, path):
     assert_fields_close(f, o.state, TOL64)
 
 
+@pytest.mark.parametrize("rows", [1, 2, 3, 0])
+def test_fused_tile_heights_and_inflow_sides(sve, rows):
+    """The fused kernel's variant at several tile heights, with the bump's
+    inflow through the west and (mirrored) the east side."""
+    h, hu, hv, zb, dx, dy = W.dune2d(140, 70, base=0.1)
+    free = sve.BC(sve.BC_FREE)
+    p = grass(sve, 0.5, 2.5)
+    for side in ("W", "E"):
+        if side == "W":
+            case = dict(h=h, hu=hu, hv=hv, zb=zb, lx=1000.0, ly=1000.0)
+            bcs = [sve.BC(sve.BC_INFLOW, 9.9, 10.0, 0.0), free, free, free]
+        else:
+            case = dict(h=np.ascontiguousarray(h[:, ::-1]), hu=np.ascontiguousarray(-hu[:, ::-1]),
+                        hv=np.ascontiguousarray(hv[:, ::-1]), zb=np.ascontiguousarray(zb[:, ::-1]),
+                        lx=1000.0, ly=1000.0)
+            bcs = [free, sve.BC(sve.BC_INFLOW, 9.9, -10.0, 0.0), free, free]
+        s = sve.Solver(case["h"], case["hu"], case["zb"], case["hv"], lx=1000.0, ly=1000.0,
+                       params=p, bcs=bcs)
+        s.set_tile_rows(rows)
+        s.step(40, 0.5)
+        f, t, dtl, ns = s.get_state()
+        s.close()
+        o = O.Oracle2D(case["h"], case["hu"], case["hv"], case["zb"], 1000.0 / 140, 1000.0 / 70,
+                       to_oracle_params(p), to_oracle_bcs(bcs))
+        o.step(40, 0.5)
+        assert t == pytest.approx(o.t, rel=TOL64), side
+        assert_fields_close(f, o.state, TOL64)
+
+
 @pytest.mark.parametrize("path", ["fused", "split"])
 def test_mpm_channel(sve, path):
     lx, ly = 4000.0 * 160 / 8192, 1000.0 * 70 / 2048
