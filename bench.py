@@ -266,6 +266,71 @@ def dune1d_leg(args, sve, torch):
     return out
 
 
+# CFL-0.5 steps of the paper's 1D antidune (2400 cells) from t = 0 to T = 50 s,
+# the last one clipped to land on T (the oracle's count, stored with the
+# full-size parity test's reference).
+ANTIDUNE_STEPS = 78010
+
+
+def antidune_leg(args, sve, torch):
+    """The paper's 1D antidune (subsection "1D antidune evolution"): 2400
+    cells on a 24 m channel, q0 = 1.7, h0 = 0.5, Grass A_g = 1e-3, m_g = 3,
+    inflow west / free east, CFL 0.5, to T = 50 s (one resident launch)."""
+    import workloads as W
+    h, hu, zb, dx = W.antidune1d(2400)
+    p = sve.Params(law=sve.LAW_GRASS, A_g=1e-3, m_g=3.0)
+    s = sve.Solver(h, hu, zb, lx=24.0, params=p,
+                   bcs=[sve.BC(sve.BC_INFLOW, 0.5, 1.7, 0.0), sve.BC(sve.BC_FREE)],
+                   stream=sve.current_stream_handle())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t = s.step(ANTIDUNE_STEPS, 0.5, 50.0)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    (gh, _, gz), _, _, ns = s.get_state()
+    s.close()
+    x = (np.arange(2400) + 0.5) * dx
+    progress(f"antidune: T = {t} s in {wall:.3f} s")
+    out = {"nx": 2400, "t_end": t, "steps": int(ns), "wall_s": wall,
+           "cell_updates_per_s": 2400.0 * ns / wall, "us_per_step": wall * 1e6 / ns,
+           "crest_x_m": [float(x[np.argmax(zb)]), float(x[np.argmax(gz)])]}
+    if t != 50.0:
+        out["error"] = "the run did not end on T"
+    return out
+
+
+def laws_leg(args, sve, torch):
+    """The other threshold laws (eqs. "FLVB", "Nielsen", "Ribberink",
+    "Camenen") and the Meyer-Peter & Mueller law with the Manning and
+    Darcy-Weisbach slopes, on the MPM channel (8192 x 2048, inflow / free,
+    FP64): average launch time and HBM fraction of each closure's step."""
+    import workloads as W
+    h, hu, hv, zb, dx, dy = W.mpm_channel()
+    ny, nx = h.shape
+    bcs = [sve.BC(sve.BC_INFLOW, 0.5, 2.0, 0.0), sve.BC(sve.BC_FREE), sve.BC(sve.BC_FREE),
+           sve.BC(sve.BC_FREE)]
+    cases = (("MPM", "STRICKLER", 40.0), ("MPM", "MANNING", 0.025), ("MPM", "DARCY", 0.05),
+             ("FLVB", "STRICKLER", 40.0), ("NIELSEN", "STRICKLER", 40.0),
+             ("RIBBERINK", "STRICKLER", 40.0), ("CAMENEN", "STRICKLER", 40.0))
+    out = {"nx": nx, "ny": ny, "steps": args.laws_steps}
+    for law, fric, coef in cases:
+        p = sve.Params(law=getattr(sve, "LAW_" + law), friction=getattr(sve, "FRIC_" + fric),
+                       fric_coef=coef, d_s=1e-3, s=2.65, tau_cr=0.05)
+        s = sve.Solver(h, hu, zb, hv, lx=4000.0, ly=1000.0, params=p, bcs=bcs,
+                       stream=sve.current_stream_handle())
+        s.step(5, 0.5)
+        torch.cuda.synchronize()
+        s.step(args.laws_steps, 0.5)
+        per_launch = s.last_elapsed_ms() * 1e-3 / args.laws_steps
+        s.close()
+        out[f"{law}/{fric}"] = {"avg_launch_us": per_launch * 1e6,
+                                "cell_updates_per_s": nx * ny / per_launch,
+                                "hbm_frac": BYTES_PER_CELL_FP64 * nx * ny / per_launch / 1e9
+                                            / HBM_PEAK_GBS}
+    progress(f"laws: {len(cases)} closures x {args.laws_steps} steps")
+    return out
+
+
 def run_to(s, t_end, cfl=0.5, chunk=1000):
     """Advance solver s to t_end; returns the number of steps that advanced
     the time (chunks of `chunk` steps while they stay clear of t_end, then
@@ -489,10 +554,13 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--cpu-1d-steps", type=int, default=20000)
-    ap.add_argument("--legs", default="main,mpm,dune1d,ensemble,adjoint,paper2d,wb",
-                    help="comma list of main, mpm, dune1d, ensemble, adjoint, paper2d, wb "
-                         "(paper2d: the paper's 4000x4000 bump to T; wb: the well-balanced "
-                         "variant against the paper's scheme)")
+    ap.add_argument("--legs", default="main,mpm,dune1d,antidune,laws,ensemble,adjoint,paper2d,wb",
+                    help="comma list of main, mpm, dune1d, antidune, laws, ensemble, adjoint, "
+                         "paper2d, wb (antidune: the paper's 2400-cell 1D run to T = 50 s; "
+                         "laws: every bedload closure on the MPM channel; paper2d: the paper's "
+                         "4000x4000 bump to T; wb: the well-balanced variant against the "
+                         "paper's scheme)")
+    ap.add_argument("--laws-steps", type=int, default=50)
     ap.add_argument("--wb-steps", type=int, default=1000)
     ap.add_argument("--paper-n", type=int, default=4000)
     ap.add_argument("--paper-runs", default="scaling", choices=["scaling", "both"],
@@ -534,6 +602,10 @@ def main():
         out["mpm"] = mpm_leg(args, sve, torch)
     if "dune1d" in legs:
         out["dune1d"] = dune1d_leg(args, sve, torch)
+    if "antidune" in legs:
+        out["antidune"] = antidune_leg(args, sve, torch)
+    if "laws" in legs:
+        out["laws"] = laws_leg(args, sve, torch)
     if "ensemble" in legs:
         out["ensemble"] = ensemble_leg(args, sve, torch)
     if "adjoint" in legs:
