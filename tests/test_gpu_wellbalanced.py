@@ -246,3 +246,36 @@ def test_unsupported_entry_points_refuse_the_variant(sve):
     with pytest.raises(sve.SveError) as e:
         Ensemble([m], params=grass(sve))
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_dry_reconstruction_is_reported(sve, dim):
+    """A free surface below the neighbouring bed (h + z_b < z* at an
+    interface) reconstructs a zero depth there, which the relaxation solver
+    cannot take: the oracle raises and the library reports a step error at
+    the first step, keeping the initial state."""
+    n = 40
+    h = np.full(n, 1.0)
+    z = np.zeros(n)
+    h[20:24] = 0.2
+    z[20:24] = 1.5                     # 1.7 m free surface over a 1 m lake
+    hu = np.zeros(n)
+    p = grass(sve, 0.01)
+    if dim == 1:
+        o = O.Oracle1D(h, hu, z, 1.0, to_oracle_params(p), (O.BC(O.BC_FREE),) * 2)
+        s = sve.Solver(h, hu, z, lx=float(n), params=p, bcs=[sve.BC(sve.BC_FREE)] * 2)
+    else:
+        rep = lambda a: np.ascontiguousarray(np.repeat(a[None, :], 6, axis=0))
+        o = O.Oracle2D(rep(h), rep(hu), rep(hu), rep(z), 1.0, 1.0, to_oracle_params(p),
+                       (O.BC(O.BC_FREE),) * 4)
+        s = sve.Solver(rep(h), rep(hu), rep(z), rep(hu), lx=float(n), ly=6.0, params=p,
+                       bcs=[sve.BC(sve.BC_FREE)] * 4)
+    with pytest.raises(O.OracleError), np.errstate(all="ignore"):
+        o.step(1, 0.5)
+    with pytest.raises(sve.SveError) as e:
+        s.step(3, 0.5)
+    assert e.value.code in (-3, -4, -5)
+    fields, t, dtl, ns = s.get_state()
+    s.close()
+    assert ns == 0 and t == 0.0
+    assert np.array_equal(fields[0].ravel()[:n], h)
