@@ -15,7 +15,10 @@ The oracle follows the paper's method step by step:
     bounds (eq. "ab"), lambda = 0 projection and homogeneous Riemann
     problem per interface, cell average (section "Numerical method");
   * 2D by the method of lines on a structured mesh (section
-    "Parallelization").
+    "Parallelization");
+  * the well-balanced (hydrostatic reconstruction) and second-order
+    (MUSCL and Heun, ``oracle.second_order``) variants that the paper
+    names as future work.
 The explicit Riemann solution of the relaxation system is not printed in
 the paper; ``oracle.riemann`` derives it from the relaxation system's jump
 conditions (the derivation and the readings of silent points are listed in

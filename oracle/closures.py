@@ -59,6 +59,7 @@ class Params:
     tau_cr: float = 0.05     # critical Shields number
     momentum_friction: int = 0  # 1: semi-implicit -g h S_f in momentum
     reconstruction: int = 0  # 1: hydrostatic reconstruction at interfaces
+    order: int = 1           # 2: MUSCL reconstruction and Heun's method
 
 
 def _re(x):

@@ -46,6 +46,10 @@ bed fluxes and momentum fluxes g h^2/2 that cancel in each cell: it is kept
 for every bedload law and exponent.  On a flat bed the variant is the
 scheme itself.
 
+Second-order variant (Params.order = 2): ``oracle.second_order`` (MUSCL
+reconstruction with the minmod limiter, a cell term for the bed slope,
+Heun's method); the drivers below hand their steps to it.
+
 Storage "fp32" emulates float32 state storage with float64 arithmetic: the
 state is rounded to float32 at initialisation and after every step.
 """
@@ -299,9 +303,26 @@ class Oracle2D:
                          self.Ag)
 
     def cfl_dt(self, cfl: float) -> float:
-        X, Y = self.fluxes()
+        if self.p.order == 2:
+            from .second_order import rates_2d
+            _, X, Y = rates_2d(*self.state, self.p, self.bcs, self.dx, self.dy,
+                               self.Ag)
+        else:
+            X, Y = self.fluxes()
         return float(dt_from_speeds(np.max(X.speed), np.max(Y.speed),
                                     self.dx, self.dy, cfl))
+
+    def _heun(self, cfl=None, dt=None, t_end=None):
+        from .second_order import heun_step_2d
+        Un, dt, t_new = heun_step_2d(self.state, self.p, self.bcs, self.dx,
+                                     self.dy, self.Ag, self.nsteps, cfl=cfl,
+                                     dt=dt, t=self.t, t_end=t_end)
+        if self.storage == "fp32":
+            Un = _round32(*Un)
+        self.h, self.hu, self.hv, self.z = Un
+        self.nsteps += 1
+        self.dt_last = dt
+        self.t = t_new
 
     def _advance(self, dt: float, X, Y):
         _check(X.err, self.nsteps)
@@ -325,6 +346,9 @@ class Oracle2D:
                 self.nsteps += n - i          # remaining steps are no-ops
                 self.dt_last = 0.0
                 break
+            if self.p.order == 2:
+                self._heun(cfl=cfl, t_end=t_end)
+                continue
             X, Y = self.fluxes()
             dt = float(dt_from_speeds(np.max(X.speed), np.max(Y.speed),
                                       self.dx, self.dy, cfl))
@@ -339,6 +363,9 @@ class Oracle2D:
 
     def step_fixed_dt(self, n: int, dt: float):
         for _ in range(n):
+            if self.p.order == 2:
+                self._heun(dt=dt)
+                continue
             X, Y = self.fluxes()
             self._advance(dt, X, Y)
             self.t = self.t + dt
@@ -371,8 +398,24 @@ class Oracle1D:
         return fluxes_1d(self.h, self.hu, self.z, self.p, self.bcs, self.Ag)
 
     def cfl_dt(self, cfl: float) -> float:
-        return float(dt_from_speeds(np.max(self.fluxes().speed), None,
-                                    self.dx, None, cfl))
+        if self.p.order == 2:
+            from .second_order import rates_1d
+            _, X = rates_1d(*self.state, self.p, self.bcs, self.dx, self.Ag)
+        else:
+            X = self.fluxes()
+        return float(dt_from_speeds(np.max(X.speed), None, self.dx, None, cfl))
+
+    def _heun(self, cfl=None, dt=None, t_end=None):
+        from .second_order import heun_step_1d
+        Un, dt, t_new = heun_step_1d(self.state, self.p, self.bcs, self.dx,
+                                     self.Ag, self.nsteps, cfl=cfl, dt=dt,
+                                     t=self.t, t_end=t_end)
+        if self.storage == "fp32":
+            Un = _round32(*Un)
+        self.h, self.hu, self.z = Un
+        self.nsteps += 1
+        self.dt_last = dt
+        self.t = t_new
 
     def _advance(self, dt: float, X):
         _check(X.err, self.nsteps)
@@ -392,6 +435,9 @@ class Oracle1D:
                 self.nsteps += n - i          # remaining steps are no-ops
                 self.dt_last = 0.0
                 break
+            if self.p.order == 2:
+                self._heun(cfl=cfl, t_end=t_end)
+                continue
             X = self.fluxes()
             dt = float(dt_from_speeds(np.max(X.speed), None, self.dx, None, cfl))
             t_new = self.t + dt
@@ -405,6 +451,9 @@ class Oracle1D:
 
     def step_fixed_dt(self, n: int, dt: float):
         for _ in range(n):
+            if self.p.order == 2:
+                self._heun(dt=dt)
+                continue
             self._advance(dt, self.fluxes())
             self.t = self.t + dt
         return self.t
