@@ -86,6 +86,8 @@ typedef struct sve_params {
                                 a semi-implicit -g h S_f momentum source       */
     int    reconstruction;   /* 0: the paper's scheme; 1: well-balanced variant
                                 (hydrostatic reconstruction, see below)        */
+    int    order;            /* 1 (or 0): the paper's first-order scheme;
+                                2: second-order variant (see below)            */
 } sve_params;
 
 /*
@@ -104,6 +106,29 @@ typedef struct sve_params {
  * sve_step_fixed_dt on the fused, split and 1D resident paths (the residual
  * path runs it as fused); the adjoint, the ensemble and
  * sve_step_dev_noalloc return SVE_ERR_ARG for it.
+ *
+ * Second-order variant (order = 2).  The paper finds its first-order
+ * scheme very diffusive and names a higher order as future work (sections
+ * "Parallelization" and "Conclusions and perspectives").  The variant is the
+ * classical second-order extension: per cell and direction, minmod-limited
+ * slopes of h, u, v and the free surface h + z_b give face states; each
+ * interface solves the first-order problem (the relaxation Riemann problem,
+ * or its hydrostatic reconstruction when reconstruction = 1) between the
+ * two face states that meet there; the bed slope inside a cell adds
+ * g (h_lo + h_hi)/2 (z_hi - z_lo) to the normal momentum's flux difference;
+ * time stepping is Heun's method, U^{n+1} = (U^n + S(S(U^n)))/2 with the
+ * Euler stage S(U) = U - dt D(U) (then the optional momentum friction) and
+ * dt from the outer wave speeds of U^n's interface problems.  Two ghost
+ * layers per side, filled by the boundary rules above.  A lake at rest
+ * stays at rest (Grass m_g >= 3 and MPM with reconstruction = 0, every
+ * closure with reconstruction = 1).  Supported by sve_step and
+ * sve_step_fixed_dt in 1D and 2D, FP64 and FP32 storage, on its own pair of
+ * kernels per step (sve_set_path accepts SVE_PATH_FUSED only, the tile
+ * height of sve_set_tile_rows applies); the context then holds one more
+ * FP64 buffer of 4 nx ny values (the first stage's rate).  An error of
+ * either stage (an interface, a non-positive depth of U1 or of the new
+ * state) fails that step with the rules of sve_step.  The adjoint, the
+ * ensemble and sve_step_dev_noalloc return SVE_ERR_ARG for it.
  */
 
 typedef struct sve_bc {

@@ -31,7 +31,8 @@ class SveParams(ctypes.Structure):
                 ("m_g", ctypes.c_double), ("friction", ctypes.c_int),
                 ("fric_coef", ctypes.c_double), ("d_s", ctypes.c_double),
                 ("s", ctypes.c_double), ("tau_cr", ctypes.c_double),
-                ("momentum_friction", ctypes.c_int), ("reconstruction", ctypes.c_int)]
+                ("momentum_friction", ctypes.c_int), ("reconstruction", ctypes.c_int),
+                ("order", ctypes.c_int)]
 
 
 class SveBC(ctypes.Structure):

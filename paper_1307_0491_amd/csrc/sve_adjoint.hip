@@ -173,7 +173,7 @@ __global__ void k_zero(double* p, long long n) {
 int adjoint_supported(const sve_ctx* c) {
     const Model& M = c->M;
     if (M.dim != 2 || c->storage != SVE_FP64 || M.law != LAW_GRASS || M.momentum_friction ||
-        M.wb)
+        M.wb || M.order == 2)
         return SVE_ERR_ARG;
     for (int s = 0; s < 4; ++s)
         if (M.bc_kind[s] != BC_PERIODIC) return SVE_ERR_ARG;

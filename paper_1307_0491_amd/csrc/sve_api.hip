@@ -63,6 +63,7 @@ int sve::validate_params(const sve_params* p, int dim, const sve_bc* bc) {
     if (!(p->g > 0.0) || !std::isfinite(p->g)) return SVE_ERR_ARG;
     if (p->law < SVE_LAW_GRASS || p->law > SVE_LAW_CAMENEN) return SVE_ERR_ARG;
     if (p->reconstruction != 0 && p->reconstruction != 1) return SVE_ERR_ARG;
+    if (p->order < 0 || p->order > 2) return SVE_ERR_ARG;
     if (p->law == SVE_LAW_GRASS) {
         if (!(p->m_g >= 1.0 && p->m_g <= 4.0)) return SVE_ERR_ARG;
         if (!std::isfinite(p->A_g)) return SVE_ERR_ARG;
@@ -93,6 +94,7 @@ Model sve::make_model(int nx, int ny, double Lx, double Ly, int dim, const sve_p
     M.friction = p->friction;
     M.momentum_friction = p->momentum_friction ? 1 : 0;
     M.wb = p->reconstruction ? 1 : 0;
+    M.order = p->order == 2 ? 2 : 1;
     M.mg_is3 = (p->m_g == 3.0);
     M.mg_is1 = (p->m_g == 1.0);
     M.nx = nx;
@@ -180,8 +182,37 @@ StateView<double> rview(sve_ctx* c, int b) {
     return StateView<double>{p, p + c->pitch, p + 2 * c->pitch, p + 3 * c->pitch};
 }
 
+// Second-order steps: two kernels per step (rate of U^n and wave speeds;
+// then Heun's stages), the rate in rbuf[0].
+template <typename T>
+int run_steps_order2(sve_ctx* c, int n, double cfl, double t_end, double fixed_dt) {
+    if (!c->rbuf[0])
+        HIP_TRY(hipMalloc((void**)&c->rbuf[0], 4 * (size_t)c->pitch * sizeof(double)));
+    const int tiles_y = order2_tiles_y(c->M.nx, c->M.ny, c->M.dim, c->fused_ty,
+                                       c->wave_slots / FUSED_WAVES_PER_SIMD *
+                                           order2_waves_per_simd());
+    hipLaunchKernelGGL(k_clear_slot, dim3(1), dim3(64), 0, c->stream, c->ctrl,
+                       (int)(c->nsteps % 3));
+    (void)hipEventRecord(c->ev0, c->stream);
+    for (int s = 0; s < n; ++s) {
+        const int step = (int)(c->nsteps + s);
+        const int src = (c->cur + s) & 1, dst = src ^ 1;
+        launch_order2<T>(c->M, view_of<T>(c, src), rview(c, 0), view_of<T>(c, dst), c->Ag,
+                         c->ctrl, step, cfl, t_end, fixed_dt, tiles_y, false, c->stream);
+        launch_order2<T>(c->M, view_of<T>(c, src), rview(c, 0), view_of<T>(c, dst), c->Ag,
+                         c->ctrl, step, cfl, t_end, fixed_dt, tiles_y, true, c->stream);
+    }
+    (void)hipEventRecord(c->ev1, c->stream);
+    HIP_TRY(hipGetLastError());
+    c->speeds_valid = false;
+    c->resid_valid = false;
+    c->last_resid = false;
+    return SVE_OK;
+}
+
 template <typename T>
 int run_steps(sve_ctx* c, int n, double cfl, double t_end, double fixed_dt) {
+    if (c->M.order == 2) return run_steps_order2<T>(c, n, cfl, t_end, fixed_dt);
     const bool cfl_mode = !(fixed_dt > 0.0);
     // the residual path has no well-balanced variant: its steps run fused
     const bool resid = cfl_mode && c->path == SVE_PATH_RESIDUAL && c->M.dim == 2 && !c->M.wb;
@@ -510,6 +541,7 @@ int sve_set_path(sve_ctx* ctx, int path) {
         path != SVE_PATH_RESIDUAL)
         return SVE_ERR_ARG;
     if (path == SVE_PATH_RESIDENT && !resident_supported(ctx)) return SVE_ERR_ARG;
+    if (ctx->M.order == 2 && path != SVE_PATH_FUSED) return SVE_ERR_ARG;
     ctx->path = path;
     return SVE_OK;
 }

@@ -29,7 +29,8 @@ struct sve_ctx {
     int wave_slots = 2048;      // resident wavefronts of the step kernels on the device
     int sticky = SVE_OK;
     bool speeds_valid = false;  // slot nsteps%3 holds the speeds of the state
-    double* rbuf[2] = {nullptr, nullptr};  // residuals of the residual path (FP64, 4 fields)
+    double* rbuf[2] = {nullptr, nullptr};  // residuals of the residual path, rate D0 of the
+                                           // second-order variant (FP64, 4 fields)
     bool resid_valid = false;   // rbuf[cur] and slot nsteps%3 belong to the state
     bool last_resid = false;    // the last run_steps used the residual path
     int pending = SVE_OK;       // error of the step after the last call (residual path)
@@ -43,6 +44,18 @@ Model make_model(int nx, int ny, double Lx, double Ly, int dim, const sve_params
 // SVE_OK when the model parameters and boundary conditions are valid for a
 // grid of dimension `dim`, else SVE_ERR_ARG.
 int validate_params(const sve_params* p, int dim, const sve_bc* bc);
+
+// Second-order variant (sve_order2.hip): the number of row tiles (rows > 0:
+// tiles of that height; 0: as many as keep the launch resident, tiles of
+// at least FUSED_MIN_ROWS rows), the kernels' wavefronts per SIMD, and the
+// launch of the step's first (stage2 = false: rate D0 of U^n into R and the
+// wave speeds into slot n%3) or second kernel (U^{n+1} into D).
+int order2_tiles_y(int nx, int ny, int dim, int rows, int wave_slots);
+int order2_waves_per_simd();
+template <typename T>
+void launch_order2(const Model& M, StateView<T> S, StateView<double> R, StateView<T> D,
+                   const double* Ag, Ctrl* ctrl, int n, double cfl, double t_end,
+                   double fixed_dt, int tiles_y, bool stage2, hipStream_t stream);
 }
 
 // Frees the adjoint buffers of a context (defined with the adjoint).

@@ -204,6 +204,7 @@ __device__ __forceinline__ double dmin(double a, double b) {
 struct Model {
     int law, friction, momentum_friction;
     int wb;               // well-balanced variant (hydrostatic reconstruction)
+    int order;            // 1: the paper's first-order scheme; 2: MUSCL and Heun
     int mg_is3, mg_is1;
     int nx, ny;           // ny == 1 with dim == 1 for 1D
     int dim;

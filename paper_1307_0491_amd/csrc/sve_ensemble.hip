@@ -248,7 +248,9 @@ int sve_ens_create(sve_ens** out, int n, const sve_member* members, const sve_pa
                    void* stream) {
     if (!out || n < 1 || !members || !p) return SVE_ERR_ARG;
     *out = nullptr;
-    if (p->law != SVE_LAW_GRASS || !(p->g > 0.0) || p->reconstruction) return SVE_ERR_ARG;
+    if (p->law != SVE_LAW_GRASS || !(p->g > 0.0) || p->reconstruction ||
+        p->order == 2)
+        return SVE_ERR_ARG;
     sve_bc bc[4] = {{SVE_BC_PERIODIC, 0, 0, 0}, {SVE_BC_PERIODIC, 0, 0, 0},
                     {SVE_BC_PERIODIC, 0, 0, 0}, {SVE_BC_PERIODIC, 0, 0, 0}};
     for (int m = 0; m < n; ++m) {

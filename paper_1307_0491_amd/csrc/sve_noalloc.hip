@@ -114,7 +114,9 @@ extern "C" int sve_step_dev_noalloc(int nx, int ny, double Lx, double Ly, const 
     if (nx < 1 || ny < 1 || (long long)nx * ny > (long long)INT_MAX) return SVE_ERR_ARG;
     if (!(Lx > 0.0) || !(Ly > 0.0) || n < 0 || !(cfl > 0.0) || !std::isfinite(*t))
         return SVE_ERR_ARG;
-    if (validate_params(p, 2, bc) != SVE_OK || p->reconstruction) return SVE_ERR_ARG;
+    if (validate_params(p, 2, bc) != SVE_OK || p->reconstruction ||
+        p->order == 2)
+        return SVE_ERR_ARG;
     const long long N = (long long)nx * ny;
     double* ins[4] = {h, hu, hv, zb};
     double* outs[4] = {h_out, hu_out, hv_out, zb_out};

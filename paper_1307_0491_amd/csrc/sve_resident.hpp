@@ -221,7 +221,7 @@ k_resident_1d(Model M, StateView<T> S, StateView<T> D, const double* __restrict_
 }  // namespace sve
 
 inline bool resident_supported(const sve_ctx* c) {
-    if (c->M.dim != 1 || c->M.nx > sve::RES_NMAX) return false;
+    if (c->M.dim != 1 || c->M.nx > sve::RES_NMAX || c->M.order == 2) return false;
     int dev = 0, max_lds = 0;
     if (hipGetDevice(&dev) != hipSuccess) return false;
     if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=

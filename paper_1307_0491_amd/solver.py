@@ -29,11 +29,13 @@ class Params:
     tau_cr: float = 0.05
     momentum_friction: int = 0
     reconstruction: int = 0
+    order: int = 1
 
     def to_c(self) -> _lib.SveParams:
         return _lib.SveParams(self.law, self.g, self.A_g, self.m_g, self.friction,
                               self.fric_coef, self.d_s, self.s, self.tau_cr,
-                              self.momentum_friction, self.reconstruction)
+                              self.momentum_friction, self.reconstruction,
+                              self.order)
 
 
 @dataclasses.dataclass

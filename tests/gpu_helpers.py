@@ -20,7 +20,7 @@ def to_oracle_params(p):
     return O.Params(law=p.law, g=p.g, A_g=p.A_g, m_g=p.m_g, friction=p.friction,
                     fric_coef=p.fric_coef, d_s=p.d_s, s=p.s, tau_cr=p.tau_cr,
                     momentum_friction=p.momentum_friction,
-                    reconstruction=p.reconstruction)
+                    reconstruction=p.reconstruction, order=p.order)
 
 
 def to_oracle_bcs(bcs):
