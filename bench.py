@@ -37,6 +37,7 @@ import numpy as np  # noqa: E402
 METRIC = "cell-updates/s and % HBM roofline (FP64 2D); ensemble and adjoint vs plain"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak
 BYTES_PER_CELL_FP64 = 64.0     # read h, hu, hv, z_b and write them once (8 B each)
+O2_BYTES_PER_CELL = 160.0      # second-order step: U^n + rate (64 B), U^n + rate + U^{n+1} (96 B)
 NX = NY = 2000
 
 # HBM traffic of the fused step kernel on the main workload, from two
@@ -427,6 +428,45 @@ def wb_leg(args, sve, torch):
     return out
 
 
+def order2_leg(args, sve, torch):
+    """The second-order variant (MUSCL-minmod, Heun; two kernels per step) on
+    the main workload (periodic 2000 x 2000 Grass dune, A_g = 1e-3, m_g = 3,
+    CFL 0.5, FP64), with either interface problem, against the first-order
+    step on the same grid.  HBM bytes per cell-step of the two kernels: the
+    first reads U^n and writes the FP64 rate (64 B), the second reads U^n
+    and the rate and writes U^{n+1} (96 B)."""
+    import workloads as W
+    h, hu, hv, zb, dx, dy = W.dune2d(NX, NY)
+    bcs = [sve.BC(sve.BC_PERIODIC)] * 4
+    out = {"nx": NX, "ny": NY, "steps": args.o2_steps, "bytes_per_cell_step": O2_BYTES_PER_CELL}
+    for name, order, rec in (("first_order", 1, 0), ("second_order", 2, 0),
+                             ("second_order_well_balanced", 2, 1)):
+        p = sve.Params(law=sve.LAW_GRASS, A_g=1e-3, m_g=3.0, reconstruction=rec, order=order)
+        s = sve.Solver(h, hu, zb, hv, lx=1000.0, ly=1000.0, params=p, bcs=bcs,
+                       stream=sve.current_stream_handle())
+        s.step(20, 0.5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(args.o2_steps, 0.5)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        per_step = s.last_elapsed_ms() * 1e-3 / args.o2_steps
+        (gh, _, _, gz), t, _, _ = s.get_state()
+        s.close()
+        bpc = BYTES_PER_CELL_FP64 if order == 1 else O2_BYTES_PER_CELL
+        out[name] = {"cell_updates_per_s": NX * NY * args.o2_steps / wall,
+                     "ms_per_step": wall * 1e3 / args.o2_steps,
+                     "kernel_us_per_step": per_step * 1e6,
+                     "hbm_frac": bpc * NX * NY / per_step / 1e9 / HBM_PEAK_GBS,
+                     "sim_time_s": t, "zb_max": float(np.max(gz)),
+                     "finite": bool(np.all(np.isfinite(gh)) and np.all(gh > 0))}
+        progress(f"order2 {name}: {args.o2_steps} steps in {wall:.3f} s")
+    for name in ("second_order", "second_order_well_balanced"):
+        out[name]["cost_vs_first_order"] = (out[name]["kernel_us_per_step"]
+                                            / out["first_order"]["kernel_us_per_step"])
+    return out
+
+
 def ensemble_leg(args, sve, torch):
     import workloads as W
     from paper_1307_0491_amd.ensemble import Ensemble
@@ -554,14 +594,17 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--cpu-1d-steps", type=int, default=20000)
-    ap.add_argument("--legs", default="main,mpm,dune1d,antidune,laws,ensemble,adjoint,paper2d,wb",
+    ap.add_argument("--legs",
+                    default="main,mpm,dune1d,antidune,laws,ensemble,adjoint,paper2d,wb,order2",
                     help="comma list of main, mpm, dune1d, antidune, laws, ensemble, adjoint, "
-                         "paper2d, wb (antidune: the paper's 2400-cell 1D run to T = 50 s; "
-                         "laws: every bedload closure on the MPM channel; paper2d: the paper's "
-                         "4000x4000 bump to T; wb: the well-balanced variant against the "
-                         "paper's scheme)")
+                         "paper2d, wb, order2 (antidune: the paper's 2400-cell 1D run to T = "
+                         "50 s; laws: every bedload closure on the MPM channel; paper2d: the "
+                         "paper's 4000x4000 bump to T; wb: the well-balanced variant against the "
+                         "paper's scheme; order2: the second-order variant against the "
+                         "first-order step)")
     ap.add_argument("--laws-steps", type=int, default=50)
     ap.add_argument("--wb-steps", type=int, default=1000)
+    ap.add_argument("--o2-steps", type=int, default=1000)
     ap.add_argument("--paper-n", type=int, default=4000)
     ap.add_argument("--paper-runs", default="scaling", choices=["scaling", "both"],
                     help="scaling: A_g = 0.1 to T = 1000 s (the run of the paper's "
@@ -614,6 +657,8 @@ def main():
         out["paper2d"] = paper2d_leg(args, sve, torch)
     if "wb" in legs:
         out["wb"] = wb_leg(args, sve, torch)
+    if "order2" in legs:
+        out["order2"] = order2_leg(args, sve, torch)
     # the main leg runs after the others, on a device at its working clock
     if "main" in legs:
         wall, kern_ms, t, ns, ok = main_leg(args, sve, torch)

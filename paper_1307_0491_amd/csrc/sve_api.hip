@@ -188,9 +188,7 @@ template <typename T>
 int run_steps_order2(sve_ctx* c, int n, double cfl, double t_end, double fixed_dt) {
     if (!c->rbuf[0])
         HIP_TRY(hipMalloc((void**)&c->rbuf[0], 4 * (size_t)c->pitch * sizeof(double)));
-    const int tiles_y = order2_tiles_y(c->M.nx, c->M.ny, c->M.dim, c->fused_ty,
-                                       c->wave_slots / FUSED_WAVES_PER_SIMD *
-                                           order2_waves_per_simd());
+    const int cus = c->wave_slots / (4 * FUSED_WAVES_PER_SIMD);
     hipLaunchKernelGGL(k_clear_slot, dim3(1), dim3(64), 0, c->stream, c->ctrl,
                        (int)(c->nsteps % 3));
     (void)hipEventRecord(c->ev0, c->stream);
@@ -198,9 +196,11 @@ int run_steps_order2(sve_ctx* c, int n, double cfl, double t_end, double fixed_d
         const int step = (int)(c->nsteps + s);
         const int src = (c->cur + s) & 1, dst = src ^ 1;
         launch_order2<T>(c->M, view_of<T>(c, src), rview(c, 0), view_of<T>(c, dst), c->Ag,
-                         c->ctrl, step, cfl, t_end, fixed_dt, tiles_y, false, c->stream);
+                         c->ctrl, step, cfl, t_end, fixed_dt, c->fused_ty, cus, false,
+                         c->stream);
         launch_order2<T>(c->M, view_of<T>(c, src), rview(c, 0), view_of<T>(c, dst), c->Ag,
-                         c->ctrl, step, cfl, t_end, fixed_dt, tiles_y, true, c->stream);
+                         c->ctrl, step, cfl, t_end, fixed_dt, c->fused_ty, cus, true,
+                         c->stream);
     }
     (void)hipEventRecord(c->ev1, c->stream);
     HIP_TRY(hipGetLastError());

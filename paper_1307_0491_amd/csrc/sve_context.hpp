@@ -45,17 +45,14 @@ Model make_model(int nx, int ny, double Lx, double Ly, int dim, const sve_params
 // grid of dimension `dim`, else SVE_ERR_ARG.
 int validate_params(const sve_params* p, int dim, const sve_bc* bc);
 
-// Second-order variant (sve_order2.hip): the number of row tiles (rows > 0:
-// tiles of that height; 0: as many as keep the launch resident, tiles of
-// at least FUSED_MIN_ROWS rows), the kernels' wavefronts per SIMD, and the
-// launch of the step's first (stage2 = false: rate D0 of U^n into R and the
-// wave speeds into slot n%3) or second kernel (U^{n+1} into D).
-int order2_tiles_y(int nx, int ny, int dim, int rows, int wave_slots);
-int order2_waves_per_simd();
+// Second-order variant (sve_order2.hip): launch of the step's first
+// (stage2 = false: rate D0 of U^n into R, wave speeds into slot n%3) or
+// second kernel (U^{n+1} into D).  rows: tile height (0: automatic, from
+// the device's `cus` compute units and the kernel's occupancy).
 template <typename T>
 void launch_order2(const Model& M, StateView<T> S, StateView<double> R, StateView<T> D,
                    const double* Ag, Ctrl* ctrl, int n, double cfl, double t_end,
-                   double fixed_dt, int tiles_y, bool stage2, hipStream_t stream);
+                   double fixed_dt, int rows, int cus, bool stage2, hipStream_t stream);
 }
 
 // Frees the adjoint buffers of a context (defined with the adjoint).

@@ -45,7 +45,13 @@ namespace sve {
 namespace {
 
 constexpr int O2_OWN = 60;
-constexpr int O2_WAVES_PER_SIMD = 2;
+// Wavefronts per SIMD each kernel is built for: the first kernel of the
+// paper's interface problem with a Grass closure of exponent 1 or 3 fits
+// in 168 VGPRs (three per SIMD); the others need up to 256 (two).
+template <int CL, bool WB, bool STAGE2>
+constexpr int o2_waves() {
+    return (!STAGE2 && !WB && (CL == CL_GRASS3 || CL == CL_GRASS1)) ? 3 : 2;
+}
 
 __device__ __forceinline__ double minmod(double a, double b) {
     return a * b > 0.0 ? (fabs(a) < fabs(b) ? a : b) : 0.0;
@@ -348,7 +354,7 @@ __device__ __forceinline__ void o2_tile(const Model& M, const StateView<T>& S,
 }
 
 template <typename T, int CL, bool WB, bool STAGE2, bool D2>
-__global__ void __launch_bounds__(64, O2_WAVES_PER_SIMD)
+__global__ void __launch_bounds__(64, (o2_waves<CL, WB, STAGE2>()))
 k_o2(Model M, StateView<T> S, StateView<double> R, StateView<T> D,
      const double* __restrict__ Agf, Ctrl* ctrl, int n, double cfl, double t_end,
      double fixed_dt, int tiles_y, double rdx, double rdy) {
@@ -360,41 +366,60 @@ k_o2(Model M, StateView<T> S, StateView<double> R, StateView<T> D,
                                    blockIdx.x == 0, t % tiles_x, j0, jend, rdx, rdy);
 }
 
-template <typename T, bool WB, bool STAGE2, bool D2>
-void launch_cl(const Model& M, StateView<T> S, StateView<double> R, StateView<T> D,
-               const double* Ag, Ctrl* ctrl, int n, double cfl, double t_end, double fixed_dt,
-               int tiles_y, hipStream_t stream) {
-    const int tiles_x = (M.nx + O2_OWN - 1) / O2_OWN;
-    const int cl = closure_class(M);
-    auto kern = cl == CL_GRASS3 ? k_o2<T, CL_GRASS3, WB, STAGE2, D2>
-              : cl == CL_GRASS1 ? k_o2<T, CL_GRASS1, WB, STAGE2, D2>
-              : cl == CL_GRASSM ? k_o2<T, CL_GRASSM, WB, STAGE2, D2>
-              : cl == CL_MPM    ? k_o2<T, CL_MPM, WB, STAGE2, D2>
-                                : k_o2<T, CL_THRESH, WB, STAGE2, D2>;
-    hipLaunchKernelGGL(kern, dim3(tiles_x * tiles_y), dim3(64), 0, stream, M, S, R, D, Ag, ctrl,
-                       n, cfl, t_end, fixed_dt, tiles_y, 1.0 / M.dx, 1.0 / M.dy);
-}
-
-}  // namespace
-
-int order2_tiles_y(int nx, int ny, int dim, int rows, int wave_slots) {
+// Row tiles of a kernel: tiles of `rows` rows, or (rows = 0) as many as
+// keep every wavefront of the launch resident at once (cus x 4 SIMDs x
+// waves), with tiles of at least FUSED_MIN_ROWS rows.
+int tiles_for(int nx, int ny, int dim, int rows, int cus, int waves) {
     if (dim == 1) return 1;
     if (rows > 0) return (ny + rows - 1) / rows;
     const int tiles_x = (nx + O2_OWN - 1) / O2_OWN;
-    int T = wave_slots / tiles_x;
+    int T = cus * 4 * waves / tiles_x;
     T = T < ny / FUSED_MIN_ROWS ? T : ny / FUSED_MIN_ROWS;
     return T < 1 ? 1 : T;
 }
 
-int order2_waves_per_simd() { return O2_WAVES_PER_SIMD; }
+template <typename T, int CL, bool WB, bool STAGE2, bool D2>
+void launch_k(const Model& M, StateView<T> S, StateView<double> R, StateView<T> D,
+              const double* Ag, Ctrl* ctrl, int n, double cfl, double t_end, double fixed_dt,
+              int rows, int cus, hipStream_t stream) {
+    const int tiles_x = (M.nx + O2_OWN - 1) / O2_OWN;
+    const int tiles_y = tiles_for(M.nx, M.ny, M.dim, rows, cus, o2_waves<CL, WB, STAGE2>());
+    hipLaunchKernelGGL((k_o2<T, CL, WB, STAGE2, D2>), dim3(tiles_x * tiles_y), dim3(64), 0,
+                       stream, M, S, R, D, Ag, ctrl, n, cfl, t_end, fixed_dt, tiles_y,
+                       1.0 / M.dx, 1.0 / M.dy);
+}
+
+template <typename T, bool WB, bool STAGE2, bool D2>
+void launch_cl(const Model& M, StateView<T> S, StateView<double> R, StateView<T> D,
+               const double* Ag, Ctrl* ctrl, int n, double cfl, double t_end, double fixed_dt,
+               int rows, int cus, hipStream_t stream) {
+    const int cl = closure_class(M);
+    if (cl == CL_GRASS3)
+        launch_k<T, CL_GRASS3, WB, STAGE2, D2>(M, S, R, D, Ag, ctrl, n, cfl, t_end, fixed_dt,
+                                               rows, cus, stream);
+    else if (cl == CL_GRASS1)
+        launch_k<T, CL_GRASS1, WB, STAGE2, D2>(M, S, R, D, Ag, ctrl, n, cfl, t_end, fixed_dt,
+                                               rows, cus, stream);
+    else if (cl == CL_GRASSM)
+        launch_k<T, CL_GRASSM, WB, STAGE2, D2>(M, S, R, D, Ag, ctrl, n, cfl, t_end, fixed_dt,
+                                               rows, cus, stream);
+    else if (cl == CL_MPM)
+        launch_k<T, CL_MPM, WB, STAGE2, D2>(M, S, R, D, Ag, ctrl, n, cfl, t_end, fixed_dt, rows,
+                                            cus, stream);
+    else
+        launch_k<T, CL_THRESH, WB, STAGE2, D2>(M, S, R, D, Ag, ctrl, n, cfl, t_end, fixed_dt,
+                                               rows, cus, stream);
+}
+
+}  // namespace
 
 template <typename T>
 void launch_order2(const Model& M, StateView<T> S, StateView<double> R, StateView<T> D,
                    const double* Ag, Ctrl* ctrl, int n, double cfl, double t_end,
-                   double fixed_dt, int tiles_y, bool stage2, hipStream_t stream) {
+                   double fixed_dt, int rows, int cus, bool stage2, hipStream_t stream) {
     const bool d2 = M.dim == 2;
 #define SVE_O2(WB_, S2_, D2_) \
-    launch_cl<T, WB_, S2_, D2_>(M, S, R, D, Ag, ctrl, n, cfl, t_end, fixed_dt, tiles_y, stream)
+    launch_cl<T, WB_, S2_, D2_>(M, S, R, D, Ag, ctrl, n, cfl, t_end, fixed_dt, rows, cus, stream)
     if (M.wb) {
         if (stage2) { if (d2) SVE_O2(true, true, true); else SVE_O2(true, true, false); }
         else        { if (d2) SVE_O2(true, false, true); else SVE_O2(true, false, false); }
@@ -407,9 +432,9 @@ void launch_order2(const Model& M, StateView<T> S, StateView<double> R, StateVie
 
 template void launch_order2<double>(const Model&, StateView<double>, StateView<double>,
                                     StateView<double>, const double*, Ctrl*, int, double, double,
-                                    double, int, bool, hipStream_t);
+                                    double, int, int, bool, hipStream_t);
 template void launch_order2<float>(const Model&, StateView<float>, StateView<double>,
                                    StateView<float>, const double*, Ctrl*, int, double, double,
-                                   double, int, bool, hipStream_t);
+                                   double, int, int, bool, hipStream_t);
 
 }  // namespace sve
