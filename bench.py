@@ -464,7 +464,47 @@ def order2_leg(args, sve, torch):
     for name in ("second_order", "second_order_well_balanced"):
         out[name]["cost_vs_first_order"] = (out[name]["kernel_us_per_step"]
                                             / out["first_order"]["kernel_us_per_step"])
+    if args.o2_dune1d:
+        out["paper_1d_dune"] = o2_dune1d_accuracy(sve, torch)
     return out
+
+
+def o2_dune1d_accuracy(sve, torch):
+    """The paper's 1D dune (Grass A_g = 1, m_g = 3, periodic, T = 700 s),
+    where the paper finds J = 2000 cells diffusive and refines to 20000:
+    J = 2000 at first and second order against J = 20000 at first order
+    (averaged onto the coarse cells); L1 distance of z_b and crest."""
+    import workloads as W
+    res = {"t_end": 700.0}
+    zs = {}
+    for name, J, order in (("J20000_first_order", 20000, 1), ("J2000_first_order", 2000, 1),
+                           ("J2000_second_order", 2000, 2)):
+        h, hu, zb, dx = W.dune1d(J)
+        p = sve.Params(law=sve.LAW_GRASS, A_g=1.0, m_g=3.0, order=order)
+        s = sve.Solver(h, hu, zb, lx=1000.0, params=p, bcs=[sve.BC(sve.BC_PERIODIC)] * 2,
+                       stream=sve.current_stream_handle())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while True:
+            t, _, ns = s.times()
+            if t >= 700.0:
+                break
+            s.step(20000, 0.5, t_end=700.0)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        (_, _, z), t, _, ns = s.get_state()
+        s.close()
+        zs[name] = z
+        res[name] = {"cells": J, "order": order, "wall_s": wall, "sim_time_s": t}
+        progress(f"order2 1D dune {name}: T = {t} s in {wall:.2f} s")
+    ref = zs["J20000_first_order"].reshape(2000, 10).mean(axis=1)
+    x = W.cell_centres(2000, 1000.0)
+    res["reference_crest"] = {"z": float(ref.max()), "x": float(x[np.argmax(ref)])}
+    for name in ("J2000_first_order", "J2000_second_order"):
+        z = zs[name]
+        res[name].update({"l1_vs_J20000": float(np.mean(np.abs(z - ref))),
+                          "crest_z": float(z.max()), "crest_x": float(x[np.argmax(z)])})
+    return res
 
 
 def ensemble_leg(args, sve, torch):
@@ -605,6 +645,9 @@ def main():
     ap.add_argument("--laws-steps", type=int, default=50)
     ap.add_argument("--wb-steps", type=int, default=1000)
     ap.add_argument("--o2-steps", type=int, default=1000)
+    ap.add_argument("--o2-dune1d", type=int, default=1,
+                    help="1: also the paper's 1D dune at J = 2000, first and second order, "
+                         "against J = 20000")
     ap.add_argument("--paper-n", type=int, default=4000)
     ap.add_argument("--paper-runs", default="scaling", choices=["scaling", "both"],
                     help="scaling: A_g = 0.1 to T = 1000 s (the run of the paper's "

@@ -109,8 +109,6 @@ struct Raw {
 };
 
 // Row r of the tile: wrapped or clamped row index and the INFLOW side that
-// replaces (h, hu, hv) of a ghost row (-1 when none).
-// Row r of the tile: wrapped or clamped row index and the INFLOW side that
 // replaces (h, hu, hv) of a ghost row (-1 when none).  (The side index is
 // wave-uniform, so the model's array is read by a scalar load.)
 __device__ __forceinline__ void row_index(const Model& M, int r, int& jj, int& gin) {
