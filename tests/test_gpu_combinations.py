@@ -3,8 +3,9 @@ small 2D grid (70 x 40 cells, 20 CFL steps, default path): storage (FP64,
 FP32), closure family (Grass m_g = 3, Grass general exponent with a per-cell
 A_g field, Meyer-Peter & Mueller with Strickler, Nielsen with
 Darcy-Weisbach), boundaries (periodic; inflow west with free elsewhere),
-momentum friction (off, on) and scheme (the paper's, hydrostatic
-reconstruction).  Tolerance: 1e-12 relative L-infinity per field in FP64,
+momentum friction (off, on), interface problem (the paper's, hydrostatic
+reconstruction) and order (the paper's first order, the second-order
+variant).  Tolerance: 1e-12 relative L-infinity per field in FP64,
 1e-5 with float32 storage against the oracle's float32-storage emulation;
 the time to 1e-12 in both (each step's dt comes from the state as
 stored)."""
@@ -40,8 +41,8 @@ def case():
     return dict(h=h, hu=hu, hv=np.ascontiguousarray(hv), zb=zb, lx=lx, ly=ly)
 
 
-def params(sve, closure, friction_src, rec):
-    common = dict(momentum_friction=friction_src, reconstruction=rec)
+def params(sve, closure, friction_src, rec, order):
+    common = dict(momentum_friction=friction_src, reconstruction=rec, order=order)
     if closure == "grass3":
         return sve.Params(law=sve.LAW_GRASS, A_g=0.05, m_g=3.0, friction=sve.FRIC_MANNING,
                           fric_coef=0.03, **common)
@@ -56,13 +57,13 @@ def params(sve, closure, friction_src, rec):
 
 
 COMBOS = list(itertools.product(["fp64", "fp32"], ["grass3", "grassm", "mpm", "nielsen"],
-                                ["periodic", "inflow"], [0, 1], [0, 1]))
+                                ["periodic", "inflow"], [0, 1], [0, 1], [1, 2]))
 
 
-@pytest.mark.parametrize("storage,closure,bc,friction_src,rec", COMBOS)
-def test_switch_combination(sve, storage, closure, bc, friction_src, rec):
+@pytest.mark.parametrize("storage,closure,bc,friction_src,rec,order", COMBOS)
+def test_switch_combination(sve, storage, closure, bc, friction_src, rec, order):
     c = case()
-    p = params(sve, closure, friction_src, rec)
+    p = params(sve, closure, friction_src, rec, order)
     if bc == "periodic":
         bcs = [sve.BC(sve.BC_PERIODIC)] * 4
     else:
