@@ -241,6 +241,8 @@ def mpm_leg(args, sve, torch):
     for storage, bpc in (("fp64", 64.0), ("fp32", 32.0)):
         s = sve.Solver(h, hu, zb, hv, lx=4000.0, ly=1000.0, params=p, bcs=bcs, storage=storage,
                        stream=sve.current_stream_handle())
+        torch.cuda.synchronize()
+        device_warmup(torch, args.device_warmup_ms)
         s.step(args.mpm_warmup, 0.5)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -342,6 +344,8 @@ def laws_leg(args, sve, torch):
                        fric_coef=coef, d_s=1e-3, s=2.65, tau_cr=0.05)
         s = sve.Solver(h, hu, zb, hv, lx=4000.0, ly=1000.0, params=p, bcs=bcs,
                        stream=sve.current_stream_handle())
+        torch.cuda.synchronize()
+        device_warmup(torch, args.device_warmup_ms)
         s.step(5, 0.5)
         torch.cuda.synchronize()
         s.step(args.laws_steps, 0.5)
@@ -431,6 +435,8 @@ def wb_leg(args, sve, torch):
         p = sve.Params(law=sve.LAW_GRASS, A_g=0.1, m_g=3.0, reconstruction=rec)
         s = sve.Solver(h, hu, zb, hv, lx=1000.0, ly=1000.0, params=p, bcs=bcs,
                        stream=sve.current_stream_handle())
+        torch.cuda.synchronize()
+        device_warmup(torch, args.device_warmup_ms)
         s.step(20, 0.5)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -467,6 +473,8 @@ def order2_leg(args, sve, torch):
         p = sve.Params(law=sve.LAW_GRASS, A_g=1e-3, m_g=3.0, reconstruction=rec, order=order)
         s = sve.Solver(h, hu, zb, hv, lx=1000.0, ly=1000.0, params=p, bcs=bcs,
                        stream=sve.current_stream_handle())
+        torch.cuda.synchronize()
+        device_warmup(torch, args.device_warmup_ms)
         s.step(20, 0.5)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -607,6 +615,7 @@ def adjoint_leg(args, sve, torch):
     s.close()
     s = solver(ag0)
     torch.cuda.synchronize()
+    device_warmup(torch, args.device_warmup_ms)
     t0 = time.perf_counter()
     s.step_fixed_dt(steps, dt)
     torch.cuda.synchronize()
@@ -622,6 +631,7 @@ def adjoint_leg(args, sve, torch):
     times = []
     for it in range(2):
         torch.cuda.synchronize()
+        device_warmup(torch, args.device_warmup_ms)
         t0 = time.perf_counter()
         run.forward(steps, dt)
         zT = s.get_state_torch()[0][3]
@@ -652,8 +662,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--device-warmup-ms", type=float, default=50.0,
-                    help="FP64 matrix products before the main leg's warm-up steps, to bring "
-                         "the GPU to its working clock (0: none)")
+                    help="FP64 matrix products after each leg's set-up, before its warm-up "
+                         "steps, to bring the GPU to its working clock (0: none)")
     ap.add_argument("--rows", type=int, default=0,
                     help="tile rows of the fused kernel (0: automatic)")
     ap.add_argument("--path", default="fused", choices=["fused", "split", "residual"])
