@@ -111,6 +111,23 @@ def cpu_baseline(nsteps: int = 20):
             "seconds": el, "host": host_cpu()}
 
 
+def cpu_baseline_order2(nsteps: int = 2):
+    """The oracle's second-order variant on the same 2000 x 2000 grid over
+    `nsteps` CFL steps (bounded sample of the order2 leg's workload)."""
+    import oracle as O
+    h, hu, hv, zb = workload()
+    o = O.Oracle2D(h, hu, hv, zb, 1000.0 / NX, 1000.0 / NY,
+                   O.Params(law=O.LAW_GRASS, A_g=1e-3, m_g=3.0, order=2), (O.BC(),) * 4)
+    t0 = time.perf_counter()
+    o.step(nsteps, 0.5)
+    el = time.perf_counter() - t0
+    return {"value": NX * NY * nsteps / el, "unit": "cell-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{nsteps} second-order CFL steps of the full {NX}x{NY} grid, numpy FP64, "
+                      "one process",
+            "seconds": el}
+
+
 def cpu_baseline_1d(nsteps: int = 20000):
     """The oracle on the 1D dune (1000 cells, periodic, CFL 0.5) over the
     first `nsteps` of its 218 402 steps to T = 10000 s (bounded sample)."""
@@ -670,6 +687,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--cpu-1d-steps", type=int, default=20000)
+    ap.add_argument("--cpu-o2-steps", type=int, default=5)
     ap.add_argument("--legs",
                     default="main,mpm,dune1d,antidune,laws,ensemble,adjoint,paper2d,wb,order2",
                     help="comma list of main, mpm, dune1d, antidune, laws, ensemble, adjoint, "
@@ -787,6 +805,9 @@ def main():
     if not args.no_cpu and "dune1d" in legs:
         progress("cpu baseline 1D (oracle)")
         out["dune1d"]["cpu_baseline"] = cpu_baseline_1d(args.cpu_1d_steps)
+    if not args.no_cpu and "order2" in legs:
+        progress("cpu baseline, second order (oracle)")
+        out["order2"]["cpu_baseline"] = cpu_baseline_order2(args.cpu_o2_steps)
     print(json.dumps(out), flush=True)
 
 

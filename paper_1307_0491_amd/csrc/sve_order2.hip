@@ -31,9 +31,9 @@
 // lanes 2..61 own their column.  A lane's x-faces need lanes -/+1 (DPP
 // shifts), the x-interface (l | l+1) the high face of lane l and the low
 // face of lane l+1: owned lanes see every value they need.  Rows
-// j0-2 .. jend+1 are loaded once each (the next row while the current one
-// is computed); row c's y-faces need rows c-1 and c+1, so row c-1 is
-// completed in the iteration of row c.
+// j0-2 .. jend+1 are loaded once each (one row ahead of the computation in
+// the first kernel, two in the second); row c's y-faces need rows c-1 and
+// c+1, so row c-1 is completed in the iteration of row c.
 #include <hip/hip_runtime.h>
 
 #include "sve_context.hpp"
@@ -288,8 +288,12 @@ __device__ __forceinline__ void o2_tile(const Model& M, const StateView<T>& S,
             return w;
         };
         Row wm = load(j0 - 2), wc = load(j0 - 1), wp = load(j0);
-        int gnx;
+        // rows requested ahead: one in the first kernel, two in the second,
+        // which reads twice the bytes per row (U^n and the rate)
+        int gnx, gnx2 = -1;
         Row nxt = fetch_row<T, STAGE2, true>(M, S, R, Agf, G, ci, j0 + 1, gnx);
+        Row nxt2;
+        if (STAGE2) nxt2 = fetch_row<T, STAGE2, true>(M, S, R, Agf, G, ci, j0 + 2, gnx2);
         Prim pm = prim_of(wm), pc = prim_of(wc), pp = prim_of(wp);
         // carried from the iteration of row c-1
         Face Nf{};                   // high y-face of row c-1
@@ -343,7 +347,14 @@ __device__ __forceinline__ void o2_tile(const Model& M, const StateView<T>& S,
             pm = pc;
             pc = pp;
             pp = prim_of(wp);
-            if (c + 3 <= jend + 1) nxt = fetch_row<T, STAGE2, true>(M, S, R, Agf, G, ci, c + 3, gnx);
+            if (STAGE2) {
+                nxt = nxt2;
+                gnx = gnx2;
+                if (c + 4 <= jend + 1)
+                    nxt2 = fetch_row<T, STAGE2, true>(M, S, R, Agf, G, ci, c + 4, gnx2);
+            } else if (c + 3 <= jend + 1) {
+                nxt = fetch_row<T, STAGE2, true>(M, S, R, Agf, G, ci, c + 3, gnx);
+            }
         }
     }
     if (!STAGE2) {
