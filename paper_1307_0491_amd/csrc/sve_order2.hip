@@ -205,7 +205,6 @@ __device__ __forceinline__ void x_row(const Model& M, const Prim& pc, bool agf, 
     eX = e | dpp_u<DPP_PREV>(e);
 }
 
-template <typename T>
 __device__ __forceinline__ void store_rate(const StateView<double>& R, long long k, double h,
                                            double hu, double hv, double z, bool d2) {
     R.h[k] = h;
@@ -223,7 +222,7 @@ __device__ __forceinline__ unsigned complete(const Model& M, const StateView<dou
                                              double dt, double Dh, double Dhu, double Dhv,
                                              double Dz) {
     if (!STAGE2) {
-        store_rate<T>(R, k, Dh, Dhu, Dhv, Dz, M.dim == 2);
+        store_rate(R, k, Dh, Dhu, Dhv, Dz, M.dim == 2);
         return 0u;
     }
     double h2 = w.h - dt * Dh, hu2 = w.hu - dt * Dhu, hv2 = w.hv - dt * Dhv, z2 = w.z - dt * Dz;
