@@ -297,3 +297,36 @@ def test_unsupported_entry_points_refuse_it(sve):
     with pytest.raises(sve.SveError) as e:
         Ensemble([m], params=p)
     assert e.value.code == -1
+
+
+def test_1d_fp32_storage(sve):
+    h, hu, zb, dx = W.antidune1d(500, length=5.0)
+    p = grass(sve, 1e-3, rec=1)
+    bcs = [sve.BC(sve.BC_INFLOW, 0.5, 1.7, 0.0), sve.BC(sve.BC_FREE)]
+    s = sve.Solver(h, hu, zb, lx=5.0, params=p, bcs=bcs, storage="fp32")
+    o = O.Oracle1D(h, hu, zb, dx, to_oracle_params(p), to_oracle_bcs(bcs), storage="fp32")
+    s.step(150, 0.45)
+    o.step(150, 0.45)
+    check(s, o, TOL32)
+
+
+def test_order_field_values(sve):
+    """order 0 is the first-order scheme (bitwise equal to order 1); orders
+    other than 0, 1 and 2 are refused."""
+    case = dune(70, 40)
+    out = []
+    for order in (0, 1):
+        p = sve.Params(law=sve.LAW_GRASS, A_g=0.05, m_g=3.0, order=order)
+        s = sve.Solver(*case[:2], case[3], case[2], lx=1000.0, ly=1000.0, params=p,
+                       bcs=per(sve))
+        s.step(10, 0.5)
+        out.append(s.get_state())
+        s.close()
+    for a, b in zip(out[0][0], out[1][0]):
+        assert np.array_equal(a, b)
+    assert out[0][1] == out[1][1]
+    for order in (-1, 3):
+        with pytest.raises(sve.SveError) as e:
+            sve.Solver(*case[:2], case[3], case[2], lx=1000.0, ly=1000.0,
+                       params=sve.Params(order=order), bcs=per(sve))
+        assert e.value.code == -1
