@@ -80,13 +80,18 @@ HV_OWN_SHARE = 1e-2
 HV_OWN_TOL_FLOOR = 1e-12
 
 
-def assert_fields_close(gpu_fields, ora_fields, tol, names=("h", "hu", "hv", "z")):
+def assert_fields_close(gpu_fields, ora_fields, tol, names=("h", "hu", "hv", "z"),
+                        own_tol=None):
+    """own_tol: tolerance of hv against its own maximum (default: the parity
+    tolerance, at least HV_OWN_TOL_FLOOR); a test that loosens it states the
+    oracle's own sensitivity that justifies it."""
     errs = field_errors(gpu_fields, ora_fields, names)
     RECORDS.append(dict(errs, tol=tol, test=CURRENT_TEST))
     msg = ", ".join(f"{k} {v:.3e}" for k, v in errs.items())
     for name in names:
         assert errs[name] <= tol, f"{name}: rel Linf {errs[name]:.3e} > {tol:.1e} ({msg})"
     if "hv" in errs and errs["hv_share"] >= HV_OWN_SHARE:
-        own_tol = max(tol, HV_OWN_TOL_FLOOR)
+        if own_tol is None:
+            own_tol = max(tol, HV_OWN_TOL_FLOOR)
         assert errs["hv_own"] <= own_tol, \
             f"hv against its own maximum: {errs['hv_own']:.3e} > {own_tol:.1e} ({msg})"
