@@ -721,7 +721,7 @@ def main():
                     help="also run plain device copies of this size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); "
               "multi-GPU sharding is not built", file=sys.stderr)
         sys.exit(2)
     legs = set(args.legs.split(","))

@@ -48,7 +48,7 @@ scheme itself.
 
 Second-order variant (Params.order = 2): ``oracle.second_order`` (MUSCL
 reconstruction with the minmod limiter, a cell term for the bed slope,
-Heun's method); the drivers below hand their steps to it.
+Heun's method); Oracle1D and Oracle2D hand their steps to it.
 
 Storage "fp32" emulates float32 state storage with float64 arithmetic: the
 state is rounded to float32 at initialisation and after every step.

@@ -17,7 +17,7 @@ slope, Heun's method).  None of them re-types the module's formulas:
     scheme's update divided by dt;
   * a y-uniform 2D run equals the 1D run; transpose and mirror symmetry;
   * the first-order scheme is more diffusive (the paper's motivation);
-  * the drivers (Oracle1D / Oracle2D with order 2) take exactly these
+  * Oracle1D / Oracle2D with order 2 take exactly these
     steps, with FP32 storage rounding after each step.
 The mutation tests plant plausible slips in a copy of the module and check
 that one of these pins fails.
@@ -345,7 +345,7 @@ def test_less_diffusive_than_first_order():
     assert np.mean(np.abs(z2 - ref)) < 0.5 * np.mean(np.abs(z1 - ref))
 
 
-def test_drivers_take_these_steps():
+def test_oracle_classes_take_these_steps():
     """Oracle2D / Oracle1D with order 2 give the same states and times as the
     step functions; FP32 storage rounds after every step."""
     p = O.Params(order=2, reconstruction=1, A_g=0.02, momentum_friction=1,
