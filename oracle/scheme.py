@@ -273,7 +273,7 @@ def _round32(*arrays):
 
 
 # ----------------------------------------------------------------------------
-# Drivers
+# Time-stepping classes
 # ----------------------------------------------------------------------------
 class Oracle2D:
     """2D state (h, hu, hv, z_b) on an nx x ny grid over [0,Lx] x [0,Ly]."""
