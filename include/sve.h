@@ -197,9 +197,10 @@ int sve_get_state_dev(sve_ctx *ctx, double *h, double *hu, double *hv,
  * steps as sve_step, on a state held in caller device memory, with nothing
  * allocated by the library (no context, no hipMalloc/hipFree, no
  * allocating library routine).
- *   Scope     2D grids, FP64 state, uniform A_g (p->A_g), the fused step
- *             kernel with the automatic tile split, i.e. the arithmetic of
- *             sve_step on a context created from the same arguments.
+ *   Scope     2D grids, FP64 state, uniform A_g (p->A_g), the paper's
+ *             first-order scheme (reconstruction 0, order 0 or 1), the fused
+ *             step kernel with the automatic tile split, i.e. the arithmetic
+ *             of sve_step on a context created from the same arguments.
  *   State     h, hu, hv, zb: the initial state (nx*ny doubles each, layout as
  *             above, on the current device); they are also the second
  *             buffer of the steps and are overwritten when n >= 2.

@@ -9,7 +9,8 @@
  * the fan state at x/t = 0) are taken as in the forward step.  Supported:
  * 2D grids, FP64 storage, the Grass law (eq. "bedload Grass", uniform or
  * per-cell A_g), periodic boundaries, no momentum friction, the paper's
- * scheme (reconstruction = 0); other set-ups return SVE_ERR_ARG.
+ * first-order scheme (reconstruction = 0, order 0 or 1); other set-ups
+ * return SVE_ERR_ARG.
  *
  * Memory: the forward keeps ceil(n/k) checkpoints of the state and the
  * backward one segment of k states (k = ceil(sqrt(n)) by default), 32 bytes

@@ -41,8 +41,8 @@ typedef struct sve_ens sve_ens;
 
 /*
  * Create an ensemble of n members (n >= 1).  p: shared parameters (law must
- * be SVE_LAW_GRASS and reconstruction 0; g is used; each member's A_g and
- * m_g replace p's).  stream: hipStream_t for all work (may be NULL).
+ * be SVE_LAW_GRASS, reconstruction 0 and order 0 or 1; g is used; each
+ * member's A_g and m_g replace p's).  stream: hipStream_t for all work (may be NULL).
  * Returns SVE_ERR_ARG for invalid members (size, h <= 0, m_g outside
  * [1, 4]) or parameters.
  */
