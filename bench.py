@@ -47,16 +47,16 @@ NX = NY = 2000
 # WRITE_SIZE x 1.0000.  Valid only for the kernel sources it was taken on
 # (kernel_source_hash) and the automatic tile split; otherwise the bench
 # reports null.  Summary: profiles/k_fused_dune2000_fp64_hbm_traffic.md.
-TRAFFIC = {"src": "7834e387d9edfc94", "rows": 0,
-           "fetch_kib": 69024.7, "write_kib": 125209.0,
-           "bytes_per_launch": 269.57e6}
+TRAFFIC = {"src": "d7c187a0546313a0", "rows": 0,
+           "fetch_kib": 69004.1, "write_kib": 125208.9,
+           "bytes_per_launch": 269.53e6}
 
 # VALU activity of the same kernel, build and workload (rocprofv3 --pmc
 # SQ_INSTS_VALU, SQ_INSTS_VALU_TRANS_F64; wavefront instructions per
 # dispatch, summed over the device).  The chip issues one wave64 VALU
 # instruction per SIMD every 4 cycles (16 for FP64 transcendentals):
 # 256 CUs x 4 SIMDs at 2.4 GHz.  Summary: profiles/k_fused_dune2000_fp64_valu.md.
-VALU = {"src": "7834e387d9edfc94", "rows": 0,
+VALU = {"src": "d7c187a0546313a0", "rows": 0,
         "insts_valu": 39035198, "insts_trans_f64": 1111242}
 SIMDS = 256 * 4
 CLOCK_HZ = 2.4e9
