@@ -139,3 +139,7 @@ def test_invalid_arguments_are_rejected(sve):
     assert noalloc_run(sve, bad, params, bcs, 3, 0.5)[3] == -1
     assert noalloc_run(sve, case, params, bcs, 3, -0.5)[3] == -1
     assert noalloc_run(sve, case, params, bcs, -1, 0.5)[3] == -1
+    # the variants the entry point does not run
+    import dataclasses
+    for change in (dict(reconstruction=1), dict(order=2)):
+        assert noalloc_run(sve, case, dataclasses.replace(params, **change), bcs, 3, 0.5)[3] == -1
