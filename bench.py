@@ -38,6 +38,7 @@ METRIC = "cell-updates/s and % HBM roofline (FP64 2D); ensemble and adjoint vs p
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak
 BYTES_PER_CELL_FP64 = 64.0     # read h, hu, hv, z_b and write them once (8 B each)
 O2_BYTES_PER_CELL = 160.0      # second-order step: U^n + rate (64 B), U^n + rate + U^{n+1} (96 B)
+O2_BYTES_PER_CELL_FP32 = 112.0  # the same with float32 state (the rate stays FP64)
 NX = NY = 2000
 
 # HBM traffic of the fused step kernel on the main workload, from two
@@ -512,8 +513,48 @@ def order2_leg(args, sve, torch):
     for name in ("second_order", "second_order_well_balanced"):
         out[name]["cost_vs_first_order"] = (out[name]["kernel_us_per_step"]
                                             / out["first_order"]["kernel_us_per_step"])
+    out["mpm_channel"] = o2_mpm_channel(args, sve, torch)
     if args.o2_dune1d:
         out["paper_1d_dune"] = o2_dune1d_accuracy(sve, torch)
+    return out
+
+
+def o2_mpm_channel(args, sve, torch):
+    """The second-order variant on the MPM channel (8192 x 2048 cells,
+    inflow / free, FP64 and FP32 storage) beside the first-order step."""
+    import workloads as W
+    h, hu, hv, zb, dx, dy = W.mpm_channel()
+    ny, nx = h.shape
+    bcs = [sve.BC(sve.BC_INFLOW, 0.5, 2.0, 0.0), sve.BC(sve.BC_FREE), sve.BC(sve.BC_FREE),
+           sve.BC(sve.BC_FREE)]
+    steps = max(1, args.o2_steps // 5)
+    out = {"nx": nx, "ny": ny, "steps": steps}
+    for name, order, storage, bpc in (("first_order_fp64", 1, "fp64", BYTES_PER_CELL_FP64),
+                                      ("second_order_fp64", 2, "fp64", O2_BYTES_PER_CELL),
+                                      ("second_order_fp32", 2, "fp32", O2_BYTES_PER_CELL_FP32)):
+        p = sve.Params(law=sve.LAW_MPM, friction=sve.FRIC_STRICKLER, fric_coef=40.0, d_s=1e-3,
+                       s=2.65, tau_cr=0.05, order=order)
+        s = sve.Solver(h, hu, zb, hv, lx=4000.0, ly=1000.0, params=p, bcs=bcs, storage=storage,
+                       stream=sve.current_stream_handle())
+        torch.cuda.synchronize()
+        device_warmup(torch, args.device_warmup_ms)
+        s.step(5, 0.45)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps, 0.45)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        per_step = s.last_elapsed_ms() * 1e-3 / steps
+        (gh, _, _, _), t, _, _ = s.get_state()
+        s.close()
+        out[name] = {"cell_updates_per_s": nx * ny * steps / wall,
+                     "kernel_us_per_step": per_step * 1e6,
+                     "hbm_frac": bpc * nx * ny / per_step / 1e9 / HBM_PEAK_GBS,
+                     "sim_time_s": t,
+                     "finite": bool(np.all(np.isfinite(gh)) and np.all(gh > 0))}
+        progress(f"order2 MPM channel {name}: {steps} steps in {wall:.3f} s")
+    out["second_order_cost_vs_first_order"] = (out["second_order_fp64"]["kernel_us_per_step"]
+                                               / out["first_order_fp64"]["kernel_us_per_step"])
     return out
 
 

@@ -46,11 +46,12 @@ namespace {
 
 constexpr int O2_OWN = 60;
 // Wavefronts per SIMD each kernel is built for: the first kernel of the
-// paper's interface problem with a Grass closure of exponent 1 or 3 fits
-// in 168 VGPRs (three per SIMD); the others need up to 256 (two).
+// paper's interface problem with the Grass closure of exponent 1 or 3 or
+// the Meyer-Peter & Mueller closure fits in 168 VGPRs (three per SIMD);
+// the others need up to 256 (two).
 template <int CL, bool WB, bool STAGE2>
 constexpr int o2_waves() {
-    return (!STAGE2 && !WB && (CL == CL_GRASS3 || CL == CL_GRASS1)) ? 3 : 2;
+    return (!STAGE2 && !WB && (CL == CL_GRASS3 || CL == CL_GRASS1 || CL == CL_MPM)) ? 3 : 2;
 }
 
 __device__ __forceinline__ double minmod(double a, double b) {
