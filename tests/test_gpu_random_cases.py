@@ -1,0 +1,109 @@
+"""Seeded random configurations against the oracle: grid shapes from 1 to
+200 cells per side (tile edges, ragged tiles, single rows and columns),
+boundary kinds per direction (periodic pairs, or free / inflow on each
+side), closure family, interface problem, order, storage, momentum
+friction, tile height and CFL number drawn per case; smooth random states
+(subcritical flow over a random bed).  FP64 at 1e-12, float32 storage at
+1e-5 against the oracle's emulation; the time to 1e-12."""
+import numpy as np
+import pytest
+
+import oracle as O
+from gpu_helpers import assert_fields_close, to_oracle_bcs, to_oracle_params
+
+pytestmark = pytest.mark.gpu
+
+N_CASES = 200
+
+
+@pytest.fixture(scope="module")
+def sve(gpu_lib):
+    return gpu_lib
+
+
+def smooth(rng, ny, nx, amp):
+    """A smooth random field: a few low Fourier modes."""
+    y = (np.arange(ny) + 0.5)[:, None] / max(ny, 1)
+    x = (np.arange(nx) + 0.5)[None, :] / max(nx, 1)
+    f = np.zeros((ny, nx))
+    for _ in range(4):
+        kx, ky = rng.integers(0, 3, 2)
+        ph = rng.uniform(0, 2 * np.pi)
+        f += rng.uniform(-1, 1) * np.cos(2 * np.pi * (kx * x + ky * y) + ph)
+    return amp * f / 4.0
+
+
+def draw(sve, seed):
+    rng = np.random.default_rng(1000 + seed)
+    nx = int(rng.choice([1, 2, 3, 7, 59, 60, 61, 62, 63, 64, 121, 130, 200]))
+    ny = int(rng.choice([1, 2, 3, 5, 8, 9, 17, 33, 64, 150]))
+    dx = float(rng.uniform(2.0, 10.0))
+    dy = float(rng.uniform(2.0, 10.0))
+    zb = 0.3 + smooth(rng, ny, nx, 0.3)
+    h = 2.0 + smooth(rng, ny, nx, 0.4) - (zb - 0.3)
+    u = 0.8 + smooth(rng, ny, nx, 0.5)
+    v = smooth(rng, ny, nx, 0.4)
+    bcs = []
+    for pair in range(2):
+        if rng.uniform() < 0.5:
+            bcs += [sve.BC(sve.BC_PERIODIC)] * 2
+        else:
+            for _ in range(2):
+                if rng.uniform() < 0.4:
+                    bcs.append(sve.BC(sve.BC_INFLOW, 2.0, 1.6 if pair == 0 else 0.2,
+                                      0.1 if pair == 0 else 1.2))
+                else:
+                    bcs.append(sve.BC(sve.BC_FREE))
+    closure = rng.choice(["grass3", "grassm", "mpm", "nielsen"])
+    common = dict(reconstruction=int(rng.integers(0, 2)), order=int(rng.integers(1, 3)),
+                  momentum_friction=int(rng.uniform() < 0.3))
+    if closure == "grass3":
+        p = sve.Params(law=sve.LAW_GRASS, A_g=float(rng.uniform(0.01, 0.1)), m_g=3.0,
+                       friction=sve.FRIC_MANNING, fric_coef=0.03, **common)
+    elif closure == "grassm":
+        p = sve.Params(law=sve.LAW_GRASS, A_g=float(rng.uniform(0.01, 0.1)),
+                       m_g=float(rng.uniform(1.5, 4.0)), friction=sve.FRIC_DARCY,
+                       fric_coef=0.05, **common)
+    elif closure == "mpm":
+        p = sve.Params(law=sve.LAW_MPM, friction=sve.FRIC_STRICKLER, fric_coef=40.0, d_s=1e-3,
+                       s=2.65, tau_cr=0.05, **common)
+    else:
+        p = sve.Params(law=sve.LAW_NIELSEN, friction=sve.FRIC_DARCY, fric_coef=0.05,
+                       d_s=1e-3, s=2.65, tau_cr=0.05, **common)
+    storage = "fp32" if rng.uniform() < 0.25 else "fp64"
+    rows = int(rng.choice([0, 0, 1, 2, 3, 5, 16]))
+    cfl = float(rng.uniform(0.2, 0.5))
+    steps = int(rng.integers(3, 16))
+    return dict(h=h, hu=h * u, hv=h * v, zb=zb, dx=dx, dy=dy, bcs=bcs, p=p, storage=storage,
+                rows=rows, cfl=cfl, steps=steps)
+
+
+@pytest.mark.parametrize("seed", range(N_CASES))
+def test_random_configuration(sve, seed):
+    c = draw(sve, seed)
+    ny, nx = c["h"].shape
+    s = sve.Solver(c["h"], c["hu"], c["zb"], c["hv"], lx=c["dx"] * nx, ly=c["dy"] * ny,
+                   params=c["p"], bcs=c["bcs"], storage=c["storage"])
+    s.set_tile_rows(c["rows"])
+    o = O.Oracle2D(c["h"], c["hu"], c["hv"], c["zb"], c["dx"], c["dy"], to_oracle_params(c["p"]),
+                   to_oracle_bcs(c["bcs"]), storage=c["storage"])
+    try:
+        with np.errstate(all="ignore"):
+            o.step(c["steps"], c["cfl"])
+        oracle_error = None
+    except O.OracleError as e:
+        oracle_error = e
+    if oracle_error is not None:
+        # the library fails at the same step and keeps the state before it
+        with pytest.raises(sve.SveError):
+            s.step(c["steps"], c["cfl"])
+        f, t, dtl, ns = s.get_state()
+        s.close()
+        assert ns == oracle_error.step
+        return
+    s.step(c["steps"], c["cfl"])
+    f, t, dtl, ns = s.get_state()
+    s.close()
+    assert ns == c["steps"]
+    assert t == pytest.approx(o.t, rel=1e-12)
+    assert_fields_close(f, o.state, 1e-12 if c["storage"] == "fp64" else 1e-5)
