@@ -1,10 +1,15 @@
-"""Seeded random configurations against the oracle: grid shapes from 1 to
-200 cells per side (tile edges, ragged tiles, single rows and columns),
+"""Seeded random configurations against the oracle.  2D (200 cases): grid
+shapes from 1 to 200 cells per side (tile edges, ragged tiles, single rows
+and columns),
 boundary kinds per direction (periodic pairs, or free / inflow on each
 side), closure family, interface problem, order, storage, momentum
 friction, tile height and CFL number drawn per case; smooth random states
-(subcritical flow over a random bed).  FP64 at 1e-12, float32 storage at
-1e-5 against the oracle's emulation; the time to 1e-12."""
+(subcritical flow over a random bed).  1D (60 cases): 1 to 3000 cells
+(around the workgroup width of the LDS-resident kernel and its size limit),
+periodic or inflow / free, the three closure families, both interface
+problems and orders, storage, friction, the resident or split path.  FP64
+at 1e-12, float32 storage at 1e-5 against the oracle's emulation; the time
+to 1e-12.  A case the oracle rejects must fail at the same step."""
 import numpy as np
 import pytest
 
@@ -107,3 +112,66 @@ def test_random_configuration(sve, seed):
     assert ns == c["steps"]
     assert t == pytest.approx(o.t, rel=1e-12)
     assert_fields_close(f, o.state, 1e-12 if c["storage"] == "fp64" else 1e-5)
+
+
+def draw1d(sve, seed):
+    rng = np.random.default_rng(5000 + seed)
+    nx = int(rng.choice([1, 2, 3, 59, 60, 61, 64, 65, 1000, 1023, 1024, 1025, 2000, 2922, 3000]))
+    dx = float(rng.uniform(0.5, 10.0))
+    zb = 0.3 + smooth(rng, 1, nx, 0.3)[0]
+    h = 2.0 + smooth(rng, 1, nx, 0.4)[0] - (zb - 0.3)
+    u = 0.8 + smooth(rng, 1, nx, 0.5)[0]
+    if rng.uniform() < 0.5:
+        bcs = [sve.BC(sve.BC_PERIODIC)] * 2
+    else:
+        bcs = [sve.BC(sve.BC_INFLOW, 2.0, 1.6, 0.0) if rng.uniform() < 0.5 else sve.BC(sve.BC_FREE),
+               sve.BC(sve.BC_FREE)]
+    closure = rng.choice(["grass3", "grassm", "mpm"])
+    common = dict(reconstruction=int(rng.integers(0, 2)), order=int(rng.integers(1, 3)),
+                  momentum_friction=int(rng.uniform() < 0.3))
+    if closure == "grass3":
+        p = sve.Params(law=sve.LAW_GRASS, A_g=float(rng.uniform(0.01, 0.1)), m_g=3.0,
+                       friction=sve.FRIC_MANNING, fric_coef=0.03, **common)
+    elif closure == "grassm":
+        p = sve.Params(law=sve.LAW_GRASS, A_g=float(rng.uniform(0.01, 0.1)),
+                       m_g=float(rng.uniform(1.5, 4.0)), friction=sve.FRIC_DARCY,
+                       fric_coef=0.05, **common)
+    else:
+        p = sve.Params(law=sve.LAW_MPM, friction=sve.FRIC_STRICKLER, fric_coef=40.0, d_s=1e-3,
+                       s=2.65, tau_cr=0.05, **common)
+    storage = "fp32" if rng.uniform() < 0.25 else "fp64"
+    split = p.order == 1 and rng.uniform() < 0.4
+    return dict(h=h, hu=h * u, zb=zb, dx=dx, bcs=bcs, p=p, storage=storage, split=split,
+                cfl=float(rng.uniform(0.2, 0.5)), steps=int(rng.integers(3, 40)))
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_random_configuration_1d(sve, seed):
+    c = draw1d(sve, seed)
+    nx = c["h"].shape[0]
+    s = sve.Solver(c["h"], c["hu"], c["zb"], lx=c["dx"] * nx, params=c["p"], bcs=c["bcs"],
+                   storage=c["storage"])
+    if c["split"]:
+        s.set_path(sve.PATH_SPLIT)
+    o = O.Oracle1D(c["h"], c["hu"], c["zb"], c["dx"], to_oracle_params(c["p"]),
+                   to_oracle_bcs(c["bcs"]), storage=c["storage"])
+    try:
+        with np.errstate(all="ignore"):
+            o.step(c["steps"], c["cfl"])
+        oracle_error = None
+    except O.OracleError as e:
+        oracle_error = e
+    if oracle_error is not None:
+        with pytest.raises(sve.SveError):
+            s.step(c["steps"], c["cfl"])
+        f, t, dtl, ns = s.get_state()
+        s.close()
+        assert ns == oracle_error.step
+        return
+    s.step(c["steps"], c["cfl"])
+    f, t, dtl, ns = s.get_state()
+    s.close()
+    assert ns == c["steps"]
+    assert t == pytest.approx(o.t, rel=1e-12)
+    assert_fields_close(f, o.state, 1e-12 if c["storage"] == "fp64" else 1e-5,
+                        names=("h", "hu", "z"))
