@@ -32,8 +32,8 @@
 // shifts), the x-interface (l | l+1) the high face of lane l and the low
 // face of lane l+1: owned lanes see every value they need.  Rows
 // j0-2 .. jend+1 are loaded once each (one row ahead of the computation in
-// the first kernel, two in the second); row c's y-faces need rows c-1 and
-// c+1, so row c-1 is completed in the iteration of row c.
+// the first kernel, two in most forms of the second); row c's y-faces need
+// rows c-1 and c+1, so row c-1 is completed in the iteration of row c.
 #include <hip/hip_runtime.h>
 
 #include "sve_context.hpp"
@@ -289,11 +289,17 @@ __device__ __forceinline__ void o2_tile(const Model& M, const StateView<T>& S,
         };
         Row wm = load(j0 - 2), wc = load(j0 - 1), wp = load(j0);
         // rows requested ahead: one in the first kernel, two in the second,
-        // which reads twice the bytes per row (U^n and the rate)
+        // which reads twice the bytes per row (U^n and the rate), except
+        // with the general Grass exponent and the run-time threshold laws,
+        // whose closures leave no room for the second row's registers (it
+        // spilled 7 to 21 VGPRs; one row ahead: general exponent 323 ->
+        // 313 us per 2000^2 step, 350 -> 314 us with the hydrostatic
+        // reconstruction)
         int gnx, gnx2 = -1;
+        constexpr bool AHEAD2 = STAGE2 && CL != CL_GRASSM && CL != CL_THRESH;
         Row nxt = fetch_row<T, STAGE2, true>(M, S, R, Agf, G, ci, j0 + 1, gnx);
         Row nxt2;
-        if (STAGE2) nxt2 = fetch_row<T, STAGE2, true>(M, S, R, Agf, G, ci, j0 + 2, gnx2);
+        if (AHEAD2) nxt2 = fetch_row<T, STAGE2, true>(M, S, R, Agf, G, ci, j0 + 2, gnx2);
         Prim pm = prim_of(wm), pc = prim_of(wc), pp = prim_of(wp);
         // carried from the iteration of row c-1
         Face Nf{};                   // high y-face of row c-1
@@ -347,7 +353,7 @@ __device__ __forceinline__ void o2_tile(const Model& M, const StateView<T>& S,
             pm = pc;
             pc = pp;
             pp = prim_of(wp);
-            if (STAGE2) {
+            if (AHEAD2) {
                 nxt = nxt2;
                 gnx = gnx2;
                 if (c + 4 <= jend + 1)
