@@ -21,6 +21,15 @@ constexpr int RES_BLOCK = 1024;
 constexpr int RES_PER_THREAD = 3;
 constexpr int RES_NMAX = RES_BLOCK * RES_PER_THREAD;
 
+// Threads of the workgroup for a closure.  1024 threads leave 128 VGPRs a
+// thread; the general Grass exponent and the run-time threshold laws need
+// more (at 1024 they spilled 17 to 48 VGPRs), so they run 512 threads with
+// six cells each.
+template <int CL>
+constexpr int res_block() {
+    return (CL == CL_GRASSM || CL == CL_THRESH) ? RES_BLOCK / 2 : RES_BLOCK;
+}
+
 // LDS layout, carved from dynamic shared memory sized for nx.
 struct ResLds {
     double *h, *hu, *z;                // nx each
@@ -63,11 +72,11 @@ __device__ __forceinline__ void res_cell(const Model& M, const ResLds& L,
     if (g >= 0 && M.bc_kind[g] == BC_INFLOW) { h = M.bc_h[g]; hu = M.bc_hu[g]; }
 }
 
-template <int CL, bool WB>
+template <int CL, bool WB, int BLOCK>
 __device__ __forceinline__ double res_max_speed(const Model& M, const ResLds& L,
                                                 const double* __restrict__ Agf) {
     double s = 0.0;
-    for (int m = threadIdx.x; m <= M.nx; m += RES_BLOCK) {
+    for (int m = threadIdx.x; m <= M.nx; m += BLOCK) {
         double h, hu, z, agA, agB;
         res_cell(M, L, Agf, m - 1, h, hu, z, agA);
         const Cell A = project<CL>(M, h, hu, 0.0, z, agA);
@@ -80,20 +89,21 @@ __device__ __forceinline__ double res_max_speed(const Model& M, const ResLds& L,
     if ((threadIdx.x & 63) == 0) L.red[threadIdx.x >> 6] = s;
     __syncthreads();
     double r = 0.0;
-    for (int w = 0; w < RES_BLOCK / 64; ++w) r = fmax(r, L.red[w]);
+    for (int w = 0; w < BLOCK / 64; ++w) r = fmax(r, L.red[w]);
     __syncthreads();
     return r;
 }
 
-template <typename T, int CL, bool WB>
-__global__ void __launch_bounds__(RES_BLOCK)
+template <typename T, int CL, bool WB, int BLOCK = res_block<CL>()>
+__global__ void __launch_bounds__(BLOCK)
 k_resident_1d(Model M, StateView<T> S, StateView<T> D, const double* __restrict__ Agf,
               Ctrl* ctrl, int n0, int nsteps, double cfl, double t_end, double fixed_dt) {
     extern __shared__ double lds_raw[];
     ResLds L = res_carve(lds_raw, M.nx);
     if (ctrl->err) return;
+    constexpr int PER_THREAD = RES_NMAX / BLOCK;
     const int nx = M.nx;
-    for (int i = threadIdx.x; i < nx; i += RES_BLOCK) {
+    for (int i = threadIdx.x; i < nx; i += BLOCK) {
         L.h[i] = (double)S.h[i];
         L.hu[i] = (double)S.hu[i];
         L.z[i] = (double)S.z[i];
@@ -116,7 +126,7 @@ k_resident_1d(Model M, StateView<T> S, StateView<T> D, const double* __restrict_
         // fluxes and outer wave speeds of the current state
         unsigned e = 0u;
         double s = 0.0;
-        for (int m = threadIdx.x; m <= nx; m += RES_BLOCK) {
+        for (int m = threadIdx.x; m <= nx; m += BLOCK) {
             double h, hu, z, agA, agB;
             res_cell(M, L, Agf, m - 1, h, hu, z, agA);
             const Cell A = project<CL>(M, h, hu, 0.0, z, agA);
@@ -140,7 +150,7 @@ k_resident_1d(Model M, StateView<T> S, StateView<T> D, const double* __restrict_
         double dt, tnew;
         if (cfl_mode) {
             S_cur = 0.0;
-            for (int w = 0; w < RES_BLOCK / 64; ++w) S_cur = fmax(S_cur, L.red[w]);
+            for (int w = 0; w < BLOCK / 64; ++w) S_cur = fmax(S_cur, L.red[w]);
             S_known = true;
             dt = cfl * M.dx / S_cur;
             tnew = t + dt;
@@ -157,10 +167,10 @@ k_resident_1d(Model M, StateView<T> S, StateView<T> D, const double* __restrict_
         // own cells here); the old state stays in registers (constant
         // indices after unrolling) until the step is known to be free of
         // errors, and is written back if it is not
-        double oh[RES_PER_THREAD], ohu[RES_PER_THREAD], oz[RES_PER_THREAD];
+        double oh[PER_THREAD], ohu[PER_THREAD], oz[PER_THREAD];
 #pragma unroll
-        for (int c = 0; c < RES_PER_THREAD; ++c) {
-            const int i = threadIdx.x + c * RES_BLOCK;
+        for (int c = 0; c < PER_THREAD; ++c) {
+            const int i = threadIdx.x + c * BLOCK;
             if (i >= nx) continue;
             oh[c] = L.h[i];
             ohu[c] = L.hu[i];
@@ -182,8 +192,8 @@ k_resident_1d(Model M, StateView<T> S, StateView<T> D, const double* __restrict_
         err = *L.err;
         if (err) {                                   // keep the state before this step
 #pragma unroll
-            for (int c = 0; c < RES_PER_THREAD; ++c) {
-                const int i = threadIdx.x + c * RES_BLOCK;
+            for (int c = 0; c < PER_THREAD; ++c) {
+                const int i = threadIdx.x + c * BLOCK;
                 if (i >= nx) continue;
                 L.h[i] = oh[c];
                 L.hu[i] = ohu[c];
@@ -197,10 +207,10 @@ k_resident_1d(Model M, StateView<T> S, StateView<T> D, const double* __restrict_
         S_known = false;
     }
     // outer wave speed of the state left in LDS, for the next call's first step
-    if (cfl_mode && !S_known) S_cur = res_max_speed<CL, WB>(M, L, Agf);
+    if (cfl_mode && !S_known) S_cur = res_max_speed<CL, WB, BLOCK>(M, L, Agf);
     // write back the last good state into the buffer the host expects
     const StateView<T>& out = (done & 1) ? D : S;
-    for (int i = threadIdx.x; i < nx; i += RES_BLOCK) {
+    for (int i = threadIdx.x; i < nx; i += BLOCK) {
         out.h[i] = (T)L.h[i];
         out.hu[i] = (T)L.hu[i];
         out.z[i] = (T)L.z[i];
@@ -252,7 +262,12 @@ void launch_resident(sve_ctx* c, int n, double cfl, double t_end, double fixed_d
                     : cl == CL_GRASSM ? k_resident_1d<T, CL_GRASSM, false>
                     : cl == CL_MPM    ? k_resident_1d<T, CL_MPM, false>
                                       : k_resident_1d<T, CL_THRESH, false>);
-    hipLaunchKernelGGL(kern, dim3(1), dim3(RES_BLOCK), lds, c->stream,
+    const int block = (cl == CL_GRASSM || cl == CL_THRESH) ? res_block<CL_GRASSM>() : RES_BLOCK;
+    static_assert(res_block<CL_GRASSM>() == res_block<CL_THRESH>() &&
+                      res_block<CL_GRASS3>() == RES_BLOCK && res_block<CL_GRASS1>() == RES_BLOCK &&
+                      res_block<CL_MPM>() == RES_BLOCK,
+                  "launch block sizes follow res_block");
+    hipLaunchKernelGGL(kern, dim3(1), dim3(block), lds, c->stream,
                        c->M, S, D, (const double*)c->Ag, c->ctrl, (int)c->nsteps, n, cfl, t_end,
                        fixed_dt);
 }
