@@ -66,11 +66,14 @@ __device__ __forceinline__ SideAdj prev_lane(const SideAdj& s) {
 // adjoint seed of an interface's fluxes comes from lambda^{n+1} of its two
 // cells: U' = U - dt/dx (F^L_{i+1/2} - F^R_{i-1/2}) - ...
 //
-// One wavefront per workgroup, two per SIMD (the register budget is 256).
-// Workgroup id runs tile xcd_tile(id) of the tiles_x x tiles_y split
-// (row-major; rows by tile_rows), so each XCD gets a contiguous band.
+// One wavefront per workgroup, two per SIMD (the register budget is 256),
+// except with the general Grass exponent, whose form needs more: at two per
+// SIMD it spilled 26 VGPRs to scratch memory; at one per SIMD the excess
+// goes to AGPRs (forward and reverse sweep of 500 steps at 1024^2: 62.1 ->
+// 56.3 ms).  Workgroup id runs tile xcd_tile(id) of the tiles_x x tiles_y
+// split (row-major; rows by tile_rows), so each XCD gets a contiguous band.
 template <int CL>
-__global__ void __launch_bounds__(64, 2)
+__global__ void __launch_bounds__(64, (CL == CL_GRASSM ? 1 : 2))
 k_adjoint_march(Model M, StateView<double> U, const double* __restrict__ Agf,
                 StateView<double> Lin, StateView<double> Lout, double* __restrict__ gAg,
                 double dt, int tiles_y) {
