@@ -385,6 +385,28 @@ def test_1d_threshold_laws_and_friction(sve, law, fric, friction_src):
         assert_fields_close(f, o.state, TOL64, names=("h", "hu", "z"))
 
 
+@pytest.mark.parametrize("closure", ["grass3", "grassm", "nielsen", "mpm"])
+def test_1d_resident_largest_grid(sve, closure):
+    """The LDS-resident kernel at the largest grid it holds (2922 cells):
+    three cells per thread in its 1024-thread form (Grass m_g = 3, MPM), six
+    in its 512-thread form (general exponent, the run-time threshold laws)."""
+    h, hu, zb, dx = W.dune1d(2922)
+    case = dict(h=h, hu=hu, zb=zb, lx=1000.0)
+    if closure == "grass3":
+        p = grass(sve, Ag=0.05)
+    elif closure == "grassm":
+        p = grass(sve, Ag=0.05, mg=2.3)
+    else:
+        p = mpm(sve, law=getattr(sve, "LAW_" + closure.upper()), friction=sve.FRIC_MANNING,
+                coef=0.025, momentum_friction=0)
+    bcs = [sve.BC(sve.BC_PERIODIC)] * 2
+    f, t, dtl, ns, o = run_pair(sve, case, p, bcs, 200, path=sve.PATH_RESIDENT)
+    assert ns == 200
+    assert t == pytest.approx(o.t, rel=TOL64)
+    assert np.max(np.abs(o.state[2] - zb)) > 1e-6           # the bed moved
+    assert_fields_close(f, o.state, TOL64, names=("h", "hu", "z"))
+
+
 def test_1d_ag_field(sve):
     """A per-cell A_g field in the 1D kernels (resident and split)."""
     h, hu, zb, dx = W.dune1d(1000)
