@@ -48,16 +48,16 @@ NX = NY = 2000
 # WRITE_SIZE x 1.0000.  Valid only for the kernel sources it was taken on
 # (kernel_source_hash) and the automatic tile split; otherwise the bench
 # reports null.  Summary: profiles/k_fused_dune2000_fp64_hbm_traffic.md.
-TRAFFIC = {"src": "d7c187a0546313a0", "rows": 0,
-           "fetch_kib": 69004.1, "write_kib": 125208.9,
-           "bytes_per_launch": 269.53e6}
+TRAFFIC = {"src": "36eed45562e5ce34", "rows": 0,
+           "fetch_kib": 69010.4, "write_kib": 125210.3,
+           "bytes_per_launch": 269.55e6}
 
 # VALU activity of the same kernel, build and workload (rocprofv3 --pmc
 # SQ_INSTS_VALU, SQ_INSTS_VALU_TRANS_F64; wavefront instructions per
 # dispatch, summed over the device).  The chip issues one wave64 VALU
 # instruction per SIMD every 4 cycles (16 for FP64 transcendentals):
 # 256 CUs x 4 SIMDs at 2.4 GHz.  Summary: profiles/k_fused_dune2000_fp64_valu.md.
-VALU = {"src": "d7c187a0546313a0", "rows": 0,
+VALU = {"src": "36eed45562e5ce34", "rows": 0,
         "insts_valu": 39035198, "insts_trans_f64": 1111242}
 SIMDS = 256 * 4
 CLOCK_HZ = 2.4e9
@@ -319,7 +319,8 @@ ANTIDUNE_STEPS = 78010
 def antidune_leg(args, sve, torch):
     """The paper's 1D antidune (subsection "1D antidune evolution"): 2400
     cells on a 24 m channel, q0 = 1.7, h0 = 0.5, Grass A_g = 1e-3, m_g = 3,
-    inflow west / free east, CFL 0.5, to T = 50 s (one resident launch)."""
+    inflow west / free east, CFL 0.5, to T = 50 s (one launch per step of
+    the one-pass 1D kernel)."""
     import workloads as W
     h, hu, zb, dx = W.antidune1d(2400)
     p = sve.Params(law=sve.LAW_GRASS, A_g=1e-3, m_g=3.0)

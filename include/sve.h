@@ -238,7 +238,7 @@ const char *sve_strerror(int code);
 
 /*
  * Path selection for tests and measurements (not needed in normal use).
- * The default is SVE_PATH_RESIDENT for 1D grids it supports, else
+ * The default is SVE_PATH_RESIDENT for 1D grids of up to 1536 cells, else
  * SVE_PATH_FUSED.
  *   SVE_PATH_FUSED   one kernel per step: update of step n and
  *                    the wave speeds of step n+1 in a single pass;

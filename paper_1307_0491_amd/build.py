@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsve.so")
 SOURCES = ["sve_api.hip", "sve_adjoint.hip", "sve_ensemble.hip", "sve_noalloc.hip",
-           "sve_order2.hip"]
+           "sve_order2.hip", "sve_fused1d.hip"]
 COMPILE_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
                  "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                  "-Wno-unused-result"]

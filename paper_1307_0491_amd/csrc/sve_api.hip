@@ -250,6 +250,9 @@ int run_steps(sve_ctx* c, int n, double cfl, double t_end, double fixed_dt) {
             } else if ((c->path == SVE_PATH_FUSED || c->path == SVE_PATH_RESIDUAL) &&
                        c->M.dim == 2) {
                 launch_fused<T>(c, src, dst, step, cfl, t_end, fixed_dt);
+            } else if (c->path == SVE_PATH_FUSED || c->path == SVE_PATH_RESIDUAL) {
+                launch_fused_1d<T>(c->M, view_of<T>(c, src), view_of<T>(c, dst), c->Ag, c->ctrl,
+                                   step, cfl, t_end, fixed_dt, c->stream);
             } else {
                 launch_update<T>(c, src, dst, step, cfl, t_end, fixed_dt);
                 if (cfl_mode) launch_speeds<T>(c, dst, (step + 1) % 3);
@@ -335,8 +338,9 @@ int init_common(sve_ctx* c, const double* h, const double* hu, const double* hv,
     launch_speeds<T>(c, 0, 0);
     HIP_TRY(hipGetLastError());
     c->speeds_valid = true;
-    // 1D grids that fit in one workgroup's LDS run on the resident kernel
-    if (resident_supported(c)) c->path = SVE_PATH_RESIDENT;
+    // small 1D grids run on the LDS-resident kernel, larger ones on the
+    // one-pass kernel (the fused path)
+    if (resident_supported(c) && c->M.nx <= RES_DEFAULT_NMAX) c->path = SVE_PATH_RESIDENT;
     return SVE_OK;
 }
 

@@ -53,6 +53,14 @@ template <typename T>
 void launch_order2(const Model& M, StateView<T> S, StateView<double> R, StateView<T> D,
                    const double* Ag, Ctrl* ctrl, int n, double cfl, double t_end,
                    double fixed_dt, int rows, int cus, bool stage2, hipStream_t stream);
+
+// One-pass 1D step (sve_fused1d.hip): update of step n from S into D and,
+// in CFL mode (fixed_dt <= 0), the wave speeds of the new state into slot
+// (n+1)%3.
+template <typename T>
+void launch_fused_1d(const Model& M, StateView<T> S, StateView<T> D, const double* Ag,
+                     Ctrl* ctrl, int n, double cfl, double t_end, double fixed_dt,
+                     hipStream_t stream);
 }
 
 // Frees the adjoint buffers of a context (defined with the adjoint).

@@ -20,6 +20,12 @@ constexpr int RES_BLOCK = 1024;
 // at most 2922 cells, so three per thread cover every grid that fits
 constexpr int RES_PER_THREAD = 3;
 constexpr int RES_NMAX = RES_BLOCK * RES_PER_THREAD;
+// Largest grid the resident kernel is chosen for by default.  Its step time
+// grows with the cells per thread (2.5, 3.7, 4.7, 6.0 and 8.4 us at 500,
+// 1000, 1500, 2000 and 2922 cells), while the one-pass 1D kernel takes
+// about 4.8 us at any size up to 20 000 cells (latency of one launch); the
+// two meet near 1500 cells.
+constexpr int RES_DEFAULT_NMAX = 1536;
 
 // Threads of the workgroup for a closure.  1024 threads leave 128 VGPRs a
 // thread; the general Grass exponent and the run-time threshold laws need

@@ -142,11 +142,12 @@ def test_residual_path_reports_errors_like_fused(sve, chunk):
         assert np.max(np.abs(a - b)) <= 1e-12 * max(1.0, np.max(np.abs(b)))
 
 
-def test_1d_resident_error_keeps_state(sve):
+@pytest.mark.parametrize("path", ["RESIDENT", "FUSED", "SPLIT"])
+def test_1d_error_keeps_state(sve, path):
     h, hu, zb, dx = W.dune1d(500)
     s = sve.Solver(h, hu, zb, lx=1000.0, params=sve.Params(A_g=0.5),
                    bcs=[sve.BC(sve.BC_PERIODIC)] * 2)
-    s.set_path(sve.PATH_RESIDENT)
+    s.set_path(getattr(sve, "PATH_" + path))
     s.step(10, 0.5)
     good, tg, _, ng = s.get_state()
     s.poke(0, 200, -1.0)

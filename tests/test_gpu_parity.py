@@ -324,7 +324,7 @@ def test_dune1d_resident_and_split(sve):
     h, hu, zb, dx = W.dune1d(1000)
     case = dict(h=h, hu=hu, zb=zb, lx=1000.0)
     bcs = [sve.BC(sve.BC_PERIODIC)] * 2
-    for path in (sve.PATH_RESIDENT, sve.PATH_SPLIT):
+    for path in (sve.PATH_RESIDENT, sve.PATH_SPLIT, sve.PATH_FUSED):
         f, t, dtl, ns, o = run_pair(sve, case, grass(sve), bcs, 3000, path=path)
         assert ns == 3000
         assert t == pytest.approx(o.t, rel=TOL64)
@@ -345,7 +345,7 @@ def test_antidune1d_inflow_free(sve):
     h, hu, zb, dx = W.antidune1d(1000)
     case = dict(h=h, hu=hu, zb=zb, lx=24.0)
     bcs = [sve.BC(sve.BC_INFLOW, 0.5, 1.7, 0.0), sve.BC(sve.BC_FREE)]
-    for path in (sve.PATH_RESIDENT, sve.PATH_SPLIT):
+    for path in (sve.PATH_RESIDENT, sve.PATH_SPLIT, sve.PATH_FUSED):
         f, t, dtl, ns, o = run_pair(sve, case, grass(sve), bcs, 2000, path=path)
         assert_fields_close(f, o.state, TOL64, names=("h", "hu", "z"))
 
@@ -357,7 +357,7 @@ def test_antidune1d_mirrored_inflow_east(sve):
     h, hu, zb, dx = W.antidune1d(1000)
     case = dict(h=h[::-1].copy(), hu=-hu[::-1], zb=zb[::-1].copy(), lx=24.0)
     bcs = [sve.BC(sve.BC_FREE), sve.BC(sve.BC_INFLOW, 0.5, -1.7, 0.0)]
-    for path in (sve.PATH_RESIDENT, sve.PATH_SPLIT):
+    for path in (sve.PATH_RESIDENT, sve.PATH_SPLIT, sve.PATH_FUSED):
         f, t, dtl, ns, o = run_pair(sve, case, grass(sve), bcs, 2000, path=path)
         assert ns == 2000
         assert t == pytest.approx(o.t, rel=TOL64)
@@ -377,7 +377,7 @@ def test_1d_threshold_laws_and_friction(sve, law, fric, friction_src):
     p = mpm(sve, law=getattr(sve, "LAW_" + law), friction=getattr(sve, "FRIC_" + fric), coef=coef,
             momentum_friction=friction_src)
     bcs = [sve.BC(sve.BC_PERIODIC)] * 2
-    for path in (sve.PATH_RESIDENT, sve.PATH_SPLIT):
+    for path in (sve.PATH_RESIDENT, sve.PATH_SPLIT, sve.PATH_FUSED):
         f, t, dtl, ns, o = run_pair(sve, case, p, bcs, 300, path=path)
         assert ns == 300
         assert t == pytest.approx(o.t, rel=TOL64)
@@ -407,6 +407,27 @@ def test_1d_resident_largest_grid(sve, closure):
     assert_fields_close(f, o.state, TOL64, names=("h", "hu", "z"))
 
 
+@pytest.mark.parametrize("nx", [3000, 6101, 20000])
+def test_1d_one_pass_large_grids(sve, nx):
+    """The one-pass 1D kernel beyond the resident kernel's size limit (its
+    default there): the periodic dune and the inflow / free antidune, on
+    grids whose last tile is full (6101 = 100 x 61 + 1 leaves one cell) or
+    ragged."""
+    h, hu, zb, dx = W.dune1d(nx)
+    case = dict(h=h, hu=hu, zb=zb, lx=1000.0)
+    f, t, dtl, ns, o = run_pair(sve, case, grass(sve, Ag=0.05), [sve.BC(sve.BC_PERIODIC)] * 2,
+                                200)
+    assert ns == 200 and t == pytest.approx(o.t, rel=TOL64)
+    assert np.max(np.abs(o.state[2] - zb)) > 1e-6
+    assert_fields_close(f, o.state, TOL64, names=("h", "hu", "z"))
+    h, hu, zb, dx = W.antidune1d(nx)
+    case = dict(h=h, hu=hu, zb=zb, lx=24.0)
+    bcs = [sve.BC(sve.BC_INFLOW, 0.5, 1.7, 0.0), sve.BC(sve.BC_FREE)]
+    f, t, dtl, ns, o = run_pair(sve, case, grass(sve), bcs, 200)
+    assert ns == 200 and t == pytest.approx(o.t, rel=TOL64)
+    assert_fields_close(f, o.state, TOL64, names=("h", "hu", "z"))
+
+
 def test_1d_ag_field(sve):
     """A per-cell A_g field in the 1D kernels (resident and split)."""
     h, hu, zb, dx = W.dune1d(1000)
@@ -414,7 +435,7 @@ def test_1d_ag_field(sve):
     rng = np.random.default_rng(9)
     Ag = 1e-2 * (1.0 + 0.5 * rng.uniform(-1, 1, h.shape))
     bcs = [sve.BC(sve.BC_PERIODIC)] * 2
-    for path in (sve.PATH_RESIDENT, sve.PATH_SPLIT):
+    for path in (sve.PATH_RESIDENT, sve.PATH_SPLIT, sve.PATH_FUSED):
         f, t, dtl, ns, o = run_pair(sve, case, grass(sve, Ag=1e-2), bcs, 500, path=path, Ag=Ag)
         assert t == pytest.approx(o.t, rel=TOL64)
         assert_fields_close(f, o.state, TOL64, names=("h", "hu", "z"))
@@ -424,7 +445,7 @@ def test_fp32_storage_1d(sve):
     h, hu, zb, dx = W.dune1d(1000)
     case = dict(h=h, hu=hu, zb=zb, lx=1000.0)
     bcs = [sve.BC(sve.BC_PERIODIC)] * 2
-    for path in (sve.PATH_RESIDENT, sve.PATH_SPLIT):
+    for path in (sve.PATH_RESIDENT, sve.PATH_SPLIT, sve.PATH_FUSED):
         f, t, dtl, ns, o = run_pair(sve, case, grass(sve, Ag=0.1), bcs, 500, path=path,
                                     storage="fp32")
         assert_fields_close(f, o.state, TOL32, names=("h", "hu", "z"))

@@ -188,7 +188,7 @@ def test_lake_at_rest_1d(sve, kind, bc):
     case = dict(h=c2["h"][0], hu=c2["hu"][0], zb=c2["zb"][0], lx=c2["lx"])
     bcs = [sve.BC(sve.BC_PERIODIC if bc == "periodic" else sve.BC_FREE)] * 2
     p = lake_params(sve, kind)
-    for path in (sve.PATH_RESIDENT, sve.PATH_SPLIT):
+    for path in (sve.PATH_RESIDENT, sve.PATH_SPLIT, sve.PATH_FUSED):
         f, t, dtl, ns, o = run_pair(sve, case, p, bcs, 1000, path=path)
         assert t == pytest.approx(o.t, rel=TOL64)
         assert rel_linf(f[0], o.h) <= TOL64 and rel_linf(f[2], o.z) <= TOL64
@@ -236,7 +236,7 @@ def test_momentum_friction_laws_1d(sve, fric, coef):
     p = sve.Params(law=sve.LAW_GRASS, A_g=1e-3, m_g=3.0, friction=getattr(sve, "FRIC_" + fric),
                    fric_coef=coef, momentum_friction=1)
     bcs = [sve.BC(sve.BC_INFLOW, 0.5, 1.7, 0.0), sve.BC(sve.BC_FREE)]
-    for path in (sve.PATH_RESIDENT, sve.PATH_SPLIT):
+    for path in (sve.PATH_RESIDENT, sve.PATH_SPLIT, sve.PATH_FUSED):
         f, t, dtl, ns, o = run_pair(sve, case, p, bcs, 1500, path=path)
         assert ns == 1500
         assert t == pytest.approx(o.t, rel=TOL64)

@@ -1,15 +1,14 @@
 """Seeded random configurations against the oracle.  2D (200 cases): grid
 shapes from 1 to 200 cells per side (tile edges, ragged tiles, single rows
-and columns),
-boundary kinds per direction (periodic pairs, or free / inflow on each
-side), closure family, interface problem, order, storage, momentum
-friction, tile height and CFL number drawn per case; smooth random states
-(subcritical flow over a random bed).  1D (60 cases): 1 to 3000 cells
-(around the workgroup width of the LDS-resident kernel and its size limit),
-periodic or inflow / free, the three closure families, both interface
-problems and orders, storage, friction, the resident or split path.  FP64
-at 1e-12, float32 storage at 1e-5 against the oracle's emulation; the time
-to 1e-12.  A case the oracle rejects must fail at the same step.  Beyond
+and columns), boundary kinds per direction (periodic pairs, or free /
+inflow on each side), closure family, interface problem, order, storage,
+momentum friction, tile height and CFL number drawn per case; smooth random
+states (subcritical flow over a random bed).  1D (60 cases): 1 to 3000
+cells (around the workgroup width of the LDS-resident kernel and its size
+limit), periodic or inflow / free, the three closure families, both
+interface problems and orders, storage, friction, the resident, split or
+one-pass path.  FP64 at 1e-12, float32 storage at 1e-5 against the
+oracle's emulation; the time to 1e-12.  A case the oracle rejects must fail at the same step.  Beyond
 the stability bound (60 cases at CFL numbers 1.2 to 3) the tolerance
 follows the oracle's own spread under a last-bit change of the input."""
 import numpy as np
@@ -142,8 +141,11 @@ def draw1d(sve, seed):
         p = sve.Params(law=sve.LAW_MPM, friction=sve.FRIC_STRICKLER, fric_coef=40.0, d_s=1e-3,
                        s=2.65, tau_cr=0.05, **common)
     storage = "fp32" if rng.uniform() < 0.25 else "fp64"
-    split = p.order == 1 and rng.uniform() < 0.4
-    return dict(h=h, hu=h * u, zb=zb, dx=dx, bcs=bcs, p=p, storage=storage, split=split,
+    # first order: the split or the one-pass path on 40 % of the draws
+    # (else the default: resident up to its size limit, one-pass beyond)
+    pick = rng.uniform() if p.order == 1 else 1.0
+    path = "SPLIT" if pick < 0.2 else "FUSED" if pick < 0.4 else None
+    return dict(h=h, hu=h * u, zb=zb, dx=dx, bcs=bcs, p=p, storage=storage, path=path,
                 cfl=float(rng.uniform(0.2, 0.5)), steps=int(rng.integers(3, 40)))
 
 
@@ -153,8 +155,8 @@ def test_random_configuration_1d(sve, seed):
     nx = c["h"].shape[0]
     s = sve.Solver(c["h"], c["hu"], c["zb"], lx=c["dx"] * nx, params=c["p"], bcs=c["bcs"],
                    storage=c["storage"])
-    if c["split"]:
-        s.set_path(sve.PATH_SPLIT)
+    if c["path"]:
+        s.set_path(getattr(sve, "PATH_" + c["path"]))
     o = O.Oracle1D(c["h"], c["hu"], c["zb"], c["dx"], to_oracle_params(c["p"]),
                    to_oracle_bcs(c["bcs"]), storage=c["storage"])
     try:
@@ -258,8 +260,8 @@ def test_random_configuration_large_cfl_1d(sve, seed):
     nx = c["h"].shape[0]
     s = sve.Solver(c["h"], c["hu"], c["zb"], lx=c["dx"] * nx, params=c["p"], bcs=c["bcs"],
                    storage=c["storage"])
-    if c["split"]:
-        s.set_path(sve.PATH_SPLIT)
+    if c["path"]:
+        s.set_path(getattr(sve, "PATH_" + c["path"]))
     P, B = to_oracle_params(c["p"]), to_oracle_bcs(c["bcs"])
 
     def make(h, hu):

@@ -187,7 +187,7 @@ def test_antidune_1d(sve):
     h, hu, zb, dx = W.antidune1d(1000)
     case = dict(h=h, hu=hu, zb=zb, lx=24.0)
     bcs = [sve.BC(sve.BC_INFLOW, 0.5, 1.7, 0.0), sve.BC(sve.BC_FREE)]
-    for path in (sve.PATH_RESIDENT, sve.PATH_SPLIT):
+    for path in (sve.PATH_RESIDENT, sve.PATH_SPLIT, sve.PATH_FUSED):
         f, t, dtl, ns, o = run_pair(sve, case, grass(sve, 1e-3), bcs, 400, path=path)
         assert ns == 400
         assert t == pytest.approx(o.t, rel=TOL64)
@@ -200,7 +200,7 @@ def test_lake_at_rest_1d(sve, kind):
     case = dict(h=c2["h"][0], hu=c2["hu"][0], zb=c2["zb"][0], lx=c2["lx"])
     p = lake_params(sve, kind)
     scale = float(np.max(case["h"] * np.sqrt(9.81 * case["h"])))
-    for path in (sve.PATH_RESIDENT, sve.PATH_SPLIT):
+    for path in (sve.PATH_RESIDENT, sve.PATH_SPLIT, sve.PATH_FUSED):
         f, t, dtl, ns, o = run_pair(sve, case, p, [sve.BC(sve.BC_FREE)] * 2, 1000, path=path)
         assert t == pytest.approx(o.t, rel=TOL64)
         assert rel_linf(f[0], o.h) <= TOL64 and rel_linf(f[2], o.z) <= TOL64
