@@ -300,6 +300,36 @@ def test_paths_and_fixed_dt_mixed_in_one_run(sve):
     assert_fields_close(f, o.state, TOL64)
 
 
+def test_1d_paths_and_fixed_dt_mixed_in_one_run(sve):
+    """Resident, one-pass, split and fixed-dt steps in one 1D run, with
+    t_end reached in the middle: each path takes over the time and the wave
+    speeds the previous one left."""
+    h, hu, zb, dx = W.dune1d(1200)
+    p = grass(sve, Ag=0.05, mg=2.5)
+    bcs = [sve.BC(sve.BC_INFLOW, 9.9, 10.0, 0.0), sve.BC(sve.BC_FREE)]
+    s = sve.Solver(h, hu, zb, lx=1000.0, params=p, bcs=bcs)
+    o = O.Oracle1D(h, hu, zb, 1000.0 / 1200, to_oracle_params(p), to_oracle_bcs(bcs))
+    plan = [("RESIDENT", 9), ("FUSED", 5), ("fixed", 3), ("FUSED", 4), ("SPLIT", 2),
+            ("RESIDENT", 3), ("fixed", 2), ("SPLIT", 3), ("FUSED", 6)]
+    for kind, n in plan:
+        if kind == "fixed":
+            s.step_fixed_dt(n, 0.02)
+            o.step_fixed_dt(n, 0.02)
+        else:
+            s.set_path(getattr(sve, "PATH_" + kind))
+            s.step(n, 0.5)
+            o.step(n, 0.5)
+    s.set_path(sve.PATH_FUSED)
+    t_end = o.t + 0.07
+    s.step(10, 0.5, t_end)
+    o.step(10, 0.5, t_end)
+    f, t, dtl, ns = s.get_state()
+    s.close()
+    assert ns == sum(n for _, n in plan) + 10
+    assert t == t_end and o.t == t_end
+    assert_fields_close(f, o.state, TOL64, names=("h", "hu", "z"))
+
+
 def test_fixed_dt_2d(sve):
     case = dune2d_case(140, 90)
     f, t, dtl, ns, o = run_pair(sve, case, grass(sve, Ag=0.02), per(sve), 50, fixed_dt=0.01)
